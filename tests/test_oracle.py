@@ -1,0 +1,251 @@
+"""Pins for the CPU oracle: each checks it against something other than itself.
+
+The paper prints no worked example, so the pins are closed forms, exact
+invariants, special cases with a known answer, brute force on tiny inputs and
+a library cross-check.  ``test_planted_mistakes_are_caught`` plants plausible
+mistakes into copies of the oracle and shows that some pin fails for each.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import eeid_oracle as O
+from paper_2002_04989_amd import inputs
+
+
+# ---------------------------------------------------------------- closed forms
+def closed_2x2(a, b, c):
+    """Eigenvalues and |v_ij|^2 of [[a, b], [conj(b), c]] from the quadratic formula."""
+    mid = 0.5 * (a + c)
+    rad = math.sqrt((0.5 * (a - c)) ** 2 + abs(b) ** 2)
+    lam = np.array([mid - rad, mid + rad])
+    W = np.empty((2, 2))
+    for i in range(2):
+        other = lam[1 - i]
+        W[i, 0] = (lam[i] - c) / (lam[i] - other)   # minor M_1 = [c]
+        W[i, 1] = (lam[i] - a) / (lam[i] - other)   # minor M_2 = [a]
+    return lam, W
+
+
+@pytest.mark.parametrize("seed", range(20))
+@pytest.mark.parametrize("cplx", [False, True])
+def test_2x2_closed_form(seed, cplx):
+    r = np.random.default_rng(seed)
+    a, c = r.standard_normal(2)
+    b = r.standard_normal() + (1j * r.standard_normal() if cplx else 0.0)
+    A = np.array([[a, np.conj(b)], [b, c]], dtype=np.complex128 if cplx else np.float64)
+    lam_x, W_x = closed_2x2(a, b, c)
+    lam, mu, W, flags = oracle.components_identity(A)
+    assert flags == 0
+    np.testing.assert_allclose(lam, lam_x, atol=1e-14, rtol=0)
+    np.testing.assert_allclose(mu[:, 0], [c, a], atol=0, rtol=0)
+    np.testing.assert_allclose(W, W_x, atol=1e-14, rtol=0)
+    w_def, W_def = oracle.components_definition(A)
+    np.testing.assert_allclose(W_def, W_x, atol=1e-14, rtol=0)
+
+
+def laplacian_closed(n):
+    """Eigenvalues, minor spectra and |v_kj|^2 of tridiag(-1, 2, -1)."""
+    k = np.arange(1, n + 1)
+    lam = 2.0 - 2.0 * np.cos(k * np.pi / (n + 1))
+    W = (2.0 / (n + 1)) * np.sin(np.outer(k, k) * np.pi / (n + 1)) ** 2   # W[k-1, j-1]
+    mu = []
+    for j in range(1, n + 1):
+        left = [2.0 - 2.0 * math.cos(q * math.pi / j) for q in range(1, j)]
+        right = [2.0 - 2.0 * math.cos(q * math.pi / (n - j + 1)) for q in range(1, n - j + 1)]
+        mu.append(sorted(left + right))
+    return lam, np.array(mu).reshape(n, n - 1), W
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 8, 64, 127])
+def test_laplacian_closed_form(n):
+    A = inputs.laplacian(n)
+    lam_x, mu_x, W_x = laplacian_closed(n)
+    lam, mu, W, flags = oracle.components_identity(A)
+    assert flags == 0
+    tol = 1e-14 + 8e-15 * n          # backward error of Jacobi grows with the rotations applied
+    np.testing.assert_allclose(lam, lam_x, atol=tol, rtol=0)
+    if n > 1:
+        np.testing.assert_allclose(mu, mu_x, atol=tol, rtol=0)
+    np.testing.assert_allclose(W, W_x, atol=1e-11, rtol=0)
+
+
+def test_diagonal_sorted_gives_identity():
+    d = np.array([-3.0, -1.0, 0.0, 0.5, 2.0, 7.0])
+    lam, mu, W, flags = oracle.components_identity(np.diag(d))
+    assert flags == 0
+    np.testing.assert_array_equal(lam, d)
+    np.testing.assert_allclose(W, np.eye(6), atol=1e-15, rtol=0)
+    assert np.all(W[~np.eye(6, dtype=bool)] == 0.0)
+
+
+def test_diagonal_unsorted_gives_permutation():
+    d = np.array([4.0, -2.0, 1.0, 9.0, -7.0])
+    order = np.argsort(d)
+    lam, mu, W, flags = oracle.components_identity(np.diag(d))
+    P = np.zeros((5, 5))
+    P[np.arange(5), order] = 1.0          # eigenvector i is e_{order[i]}
+    np.testing.assert_allclose(W, P, atol=1e-15, rtol=0)
+
+
+# ---------------------------------------------------------------- brute force
+@pytest.mark.parametrize("cplx", [False, True])
+def test_brute_force_tiny(cplx):
+    """The method against the plain definition on many tiny random matrices."""
+    worst = 0.0
+    for seed in range(300):
+        n = 1 + seed % 8
+        A = inputs.gue(n, seed) if cplx else inputs.goe(n, seed)
+        lam, mu, W, flags = oracle.components_identity(A)
+        w_def, W_def = oracle.components_definition(A)
+        assert flags == 0
+        worst = max(worst, float(np.max(np.abs(W - W_def))))
+        np.testing.assert_allclose(lam, w_def, atol=1e-13)
+    assert worst < 1e-12, worst
+
+
+# ---------------------------------------------------------------- invariants
+@pytest.mark.parametrize("family", ["goe", "wishart", "gue"])
+def test_invariants(family):
+    n = 48
+    A = getattr(inputs, family)(n, 11)
+    lam, mu, W, flags = oracle.components_identity(A)
+    assert flags == 0
+    inv = oracle.invariants(A, lam, W)
+    scale = np.max(np.abs(lam))
+    assert inv["rows"] < 1e-12 and inv["cols"] < 1e-12, inv
+    assert inv["diag"] < 1e-12 * scale and inv["frob"] < 1e-11 * scale ** 2, inv
+    assert inv["range"] < 1e-13, inv
+    mi = oracle.minor_invariants(A, lam, mu, range(n))
+    assert mi["interlace"] <= 1e-13 * scale, mi
+    assert mi["trace"] < 1e-12 * scale and mi["frob"] < 1e-11 * scale ** 2, mi
+    np.testing.assert_allclose(lam.sum(), np.real(np.trace(A)), atol=1e-12 * n * scale)
+    np.testing.assert_allclose(np.sum(lam ** 2), np.sum(np.abs(A) ** 2), rtol=1e-13)
+
+
+def test_clustered_known_eigenvectors():
+    """Q diag(lam) Q^T with tiny intra-cluster gaps: exact W is (Q**2)^T."""
+    A, lam_true, Q = inputs.clustered(192, clusters=3, gap=1e-6, seed=40)
+    lam, mu, W, flags = oracle.components_identity(A)
+    assert flags == 0
+    np.testing.assert_allclose(lam, lam_true, atol=1e-13)
+    err = np.max(np.abs(W - (Q ** 2).T))
+    assert err < 1e-8, err
+
+
+def test_degenerate_identity_matrix_flags_nan_rows():
+    lam, mu, W, flags = oracle.components_identity(np.eye(4))
+    assert flags & oracle.FLAG_DEGENERATE
+    assert np.all(np.isnan(W))
+
+
+def test_nonfinite_input_flags():
+    A = inputs.goe(5, 1)
+    A[3, 1] = np.nan
+    lam, mu, W, flags = oracle.components_identity(A)
+    assert flags & oracle.FLAG_NONFINITE_INPUT
+    assert np.all(np.isnan(W))
+
+
+def test_lower_triangle_is_read():
+    A = inputs.goe(10, 5)
+    B = A.copy()
+    B[np.triu_indices(10, 1)] = 1e6          # garbage above the diagonal
+    C = inputs.gue(10, 5)
+    D = C.copy()
+    D[np.diag_indices(10)] += 3j              # imaginary diagonal is ignored
+    D[np.triu_indices(10, 1)] = 0.0
+    for X, Y in ((A, B), (C, D)):
+        np.testing.assert_array_equal(oracle.components_identity(X)[2],
+                                      oracle.components_identity(Y)[2])
+
+
+# ---------------------------------------------------------------- library cross-checks
+@pytest.mark.parametrize("n", [5, 40, 160])
+def test_jacobi_matches_lapack(n):
+    for A in (inputs.goe(n, n), inputs.gue(n, n), inputs.wishart(n, n)):
+        w = oracle.eigvalsh(A)
+        np.testing.assert_allclose(w, np.linalg.eigvalsh(A), atol=1e-13 * n * np.max(np.abs(w)))
+
+
+def test_neumaier_matches_exact_sum():
+    r = np.random.default_rng(0)
+    x = r.standard_normal((7, 500)) * 10.0 ** r.integers(-8, 9, (7, 500))
+    got = oracle.neumaier_sum(x, axis=1)
+    want = np.array([math.fsum(row) for row in x])
+    np.testing.assert_allclose(got, want, rtol=1e-15, atol=0)
+
+
+def test_subset_of_minors_matches_full():
+    A = inputs.goe(30, 9)
+    lam, mu, W, _ = oracle.components_identity(A)
+    js = [0, 7, 29]
+    lam2, mu2, W2, _ = oracle.components_identity(A, js=js)
+    np.testing.assert_array_equal(mu2, mu[js])
+    np.testing.assert_allclose(W2, W[:, js], atol=0, rtol=0)
+
+
+# ---------------------------------------------------------------- pin sensitivity
+def _pins_pass(fn_components):
+    """Run the cheap pins against an alternative implementation; True when all hold."""
+    try:
+        for seed in range(3):
+            r = np.random.default_rng(seed)
+            a, c = r.standard_normal(2)
+            b = r.standard_normal()
+            lam_x, W_x = closed_2x2(a, b, c)
+            lam, mu, W, _ = fn_components(np.array([[a, b], [b, c]]))
+            if not np.allclose(W, W_x, atol=1e-12):
+                return False
+        lam_x, mu_x, W_x = laplacian_closed(8)
+        lam, mu, W, _ = fn_components(inputs.laplacian(8))
+        if not np.allclose(W, W_x, atol=1e-10):
+            return False
+        A = inputs.goe(6, 3)
+        lam, mu, W, _ = fn_components(A)
+        if not np.allclose(W, oracle.components_definition(A)[1], atol=1e-12):
+            return False
+        return True
+    except Exception:
+        return False
+
+
+def _variant(minor=None, combine=None, drop_last=False):
+    def comp(A):
+        A = O.hermitian_from_lower(A)
+        n = A.shape[0]
+        lam = O.eigvalsh(A)
+        mk = minor or O.minor
+        mu = np.array([O.eigvalsh(mk(A, j)) for j in range(n)]).reshape(n, n - 1)
+        if drop_last:
+            mu = mu[:, :-1]
+        D, _ = O.denominators(lam)
+        N = O.numerators(lam, mu)
+        W = np.exp(combine(N, D[:, None])) if combine else np.exp(N - D[:, None])
+        return lam, mu, W, 0
+    return comp
+
+
+def test_planted_mistakes_are_caught():
+    assert _pins_pass(lambda A: oracle.components_identity(A))
+
+    def wrong_column(A, j):               # delete row j but column j+1
+        n = A.shape[0]
+        rows = np.r_[0:j, j + 1:n]
+        cols = np.r_[0:(j + 1) % n, (j + 1) % n + 1:n]
+        M = A[np.ix_(rows, cols)]
+        return (M + M.T) / 2
+
+    def next_minor(A, j):                 # spectra assigned to the wrong j
+        return O.minor(A, (j + 1) % A.shape[0])
+
+    planted = {
+        "deleted column index off by one": _variant(minor=wrong_column),
+        "minor spectra shifted by one component": _variant(minor=next_minor),
+        "numerator and denominator swapped": _variant(combine=lambda N, D: D - N),
+        "last numerator factor dropped": _variant(drop_last=True),
+    }
+    for name, fn in planted.items():
+        assert not _pins_pass(fn), f"pins did not catch: {name}"
