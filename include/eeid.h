@@ -1,0 +1,158 @@
+/*
+ * libeeid -- squared eigenvector components of Hermitian matrices through the
+ * eigenvector-eigenvalue identity, on one AMD Instinct MI355X (gfx950).
+ *
+ * The identity (arXiv 2002.04989, Section 2, Eq. (2)): for an n x n Hermitian
+ * A with ascending eigenvalues lambda_1..lambda_n and M_j the principal minor
+ * of A with row j and column j removed,
+ *
+ *     |v_ij|^2 = prod_{k=1}^{n-1} (lambda_i(A) - lambda_k(M_j))
+ *                / prod_{k != i} (lambda_i(A) - lambda_k(A)).
+ *
+ * Algorithm 2 of Section 3 computes the spectrum of A once and the spectrum of
+ * each minor once, then evaluates the ratio.  This library does the same on
+ * the GPU: eeid_minor_eigvals computes lambda(A) and all lambda(M_j) of a batch
+ * of matrices in one persistent launch (Householder tridiagonalisation +
+ * Sturm bisection), and eeid_components evaluates the ratio for every (i, j)
+ * as a sum of logarithms of |differences| in FP64.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - C99-compatible.  Pointers named A, lambda, mu, V2 and flags are DEVICE
+ *    pointers (memory of the handle's device).  Pointers named n, a_offset and
+ *    js are HOST pointers and are only read during the call.
+ *  - Matrices are row-major with leading dimension n_b.  Only the lower
+ *    triangle (row >= column) is read; the imaginary parts of a complex
+ *    diagonal are ignored (Hermitian by convention, Section 2).
+ *    EEID_R64 elements are double; EEID_C128 elements are interleaved
+ *    (re, im) doubles and a_offset counts complex elements.
+ *  - Eigenvalues are ascending.  Outputs of a batch are densely packed in
+ *    batch order (prefix sums of n_b):
+ *      lambda: sum n_b doubles,            matrix b at offset sum_{c<b} n_c;
+ *      mu:     sum n_b (n_b - 1) doubles,  row j of matrix b = spectrum of M_j;
+ *      V2:     sum n_b^2 doubles,          V2_b[i * n_b + j] = |v_ij|^2, row i
+ *              belongs to the i-th smallest eigenvalue of A_b;
+ *      flags:  count int32 per batch (0 = clean; bits EEID_FLAG_*).
+ *  - Every call is asynchronous on the handle's stream; results are valid once
+ *    that stream has synchronised.  The caller owns A and all outputs; the
+ *    library never frees or retains them after the call returns.  The library
+ *    owns its workspace (grown lazily, freed by eeid_destroy).
+ *  - Argument errors are detected before anything is enqueued and return a
+ *    status; no C++ exception or abort crosses this interface.
+ *  - One handle is used by one host thread at a time.
+ */
+#ifndef EEID_H
+#define EEID_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct eeid_handle_s *eeid_handle_t;
+
+typedef enum {
+    EEID_OK = 0,
+    EEID_ERR_INVALID_ARG = 1,  /* null pointer, n_b < 1, count < 1, bad enum, ... */
+    EEID_ERR_NO_DEVICE = 2,    /* no usable GPU, or the device index is out of range */
+    EEID_ERR_ALLOC = 3,        /* device workspace could not be allocated */
+    EEID_ERR_HIP = 4,          /* a HIP runtime call failed; see eeid_last_error */
+    EEID_ERR_UNSUPPORTED = 5   /* valid request this build does not serve (e.g. n_b too large) */
+} eeid_status_t;
+
+typedef enum { EEID_R64 = 0, EEID_C128 = 1 } eeid_dtype_t;
+
+/* Precision of the tridiagonalisation's trailing matrix.
+ *  EEID_PREC_FP64:          everything in FP64 (the plain form).
+ *  EEID_PREC_FP32_TRAILING: the trailing matrix is stored in FP32 (FP32
+ *      complex for C128) and its rank-2k update runs on FP32 matrix cores
+ *      with FP32 accumulation; Householder vectors, norms, the tridiagonal,
+ *      the bisection and the identity stay FP64.  Eigenvalue error is of order
+ *      sqrt(n) * 2^-24 * ||A||_2. */
+typedef enum { EEID_PREC_FP64 = 0, EEID_PREC_FP32_TRAILING = 1 } eeid_prec_t;
+
+enum {
+    EEID_FLAG_NONFINITE_INPUT = 1, /* a NaN/Inf in the lower triangle: all outputs of b are NaN */
+    EEID_FLAG_DEGENERATE = 2       /* lambda_i(A) repeated exactly: row i of V2 is NaN (Eq. (2) is 0/0) */
+};
+
+/* Largest matrix order the library accepts (LDS holds two FP64/complex
+ * vectors of the padded order during tridiagonalisation). */
+#define EEID_MAX_N_R64 8192
+#define EEID_MAX_N_C128 4160
+
+/* Create a handle on HIP device `hip_device`.  Returns EEID_ERR_NO_DEVICE when
+ * no GPU is present or the index is invalid.  The handle starts on the null
+ * stream; workspace is allocated on first use. */
+eeid_status_t eeid_create(eeid_handle_t *h, int hip_device);
+
+/* Synchronise the handle's stream, free its workspace and the handle. */
+eeid_status_t eeid_destroy(eeid_handle_t h);
+
+/* Make subsequent calls enqueue on `stream` (a hipStream_t of the handle's
+ * device, passed as void*; NULL = null stream). */
+eeid_status_t eeid_set_stream(eeid_handle_t h, void *stream);
+
+/* Static description of a status code (never NULL). */
+const char *eeid_status_string(eeid_status_t s);
+
+/* Detail of the last non-OK status returned on `h` ("" if none). */
+const char *eeid_last_error(eeid_handle_t h);
+
+/* Ascending eigenvalues of every matrix of a batch (the EigenValues(A) step
+ * of Algorithms 1 and 2, Section 3).
+ *   count     number of matrices (>= 1)
+ *   n         host [count], n_b >= 1
+ *   a_offset  host [count], element offset of matrix b inside A (>= 0)
+ *   A         device, element type per `t`
+ *   lambda    device [sum n_b] output
+ *   flags     device [count] output (cleared, then EEID_FLAG_* bits) */
+eeid_status_t eeid_eigvalsh_batched(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p,
+                                    int64_t count, const int64_t *n, const int64_t *a_offset,
+                                    const void *A, double *lambda, int32_t *flags);
+
+/* lambda(A_b) and the spectra of all n_b principal minors M_j of every matrix
+ * of the batch (Section 2: M_j removes row j and column j), in one
+ * persistent launch over all (matrix, minor) problems, largest first.
+ *   mu        device [sum n_b (n_b - 1)] output, row j of b = ascending spec(M_j)
+ * Other arguments as for eeid_eigvalsh_batched. */
+eeid_status_t eeid_minor_eigvals(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p,
+                                 int64_t count, const int64_t *n, const int64_t *a_offset,
+                                 const void *A, double *lambda, double *mu, int32_t *flags);
+
+/* lambda(A) and the spectra of a chosen subset of minors of ONE matrix of
+ * order n (the single-component and single-column queries of Section 4 and
+ * Table 1 need only some minors).
+ *   nsel      number of selected minors (>= 1)
+ *   js        host [nsel], each 0 <= js[s] < n (repeats allowed)
+ *   lambda    device [n] output, or NULL to skip lambda(A)
+ *   mu_sel    device [nsel * (n - 1)] output, row s = ascending spec(M_{js[s]})
+ *   flag      device [1] output */
+eeid_status_t eeid_minor_eigvals_subset(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p,
+                                        int64_t n, const void *A, int64_t nsel, const int64_t *js,
+                                        double *lambda, double *mu_sel, int32_t *flag);
+
+/* The identity, Eq. (2): V2_b[i * n_b + j] = exp( sum_k log|lambda_i - mu_jk|
+ * - sum_{k != i} log|lambda_i - lambda_k| ) for every matrix, evaluated in
+ * FP64 with compensated sums.  An exactly zero numerator factor gives 0; an
+ * exactly repeated lambda_i gives a NaN row and sets EEID_FLAG_DEGENERATE in
+ * flags[b] (other bits are kept, so pass the flags of eeid_minor_eigvals).
+ *   lambda, mu  device, laid out as eeid_minor_eigvals writes them
+ *   V2          device [sum n_b^2] output */
+eeid_status_t eeid_components(eeid_handle_t h, int64_t count, const int64_t *n,
+                              const double *lambda, const double *mu, double *V2,
+                              int32_t *flags);
+
+/* eeid_minor_eigvals followed by eeid_components: every |v_ij|^2 of every
+ * matrix of the batch from device-resident A to device-resident V2. */
+eeid_status_t eeid_all_components(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p,
+                                  int64_t count, const int64_t *n, const int64_t *a_offset,
+                                  const void *A, double *lambda, double *mu, double *V2,
+                                  int32_t *flags);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EEID_H */

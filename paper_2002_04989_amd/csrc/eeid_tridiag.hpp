@@ -1,0 +1,633 @@
+// Batched eigenvalues of Hermitian matrices and of their principal minors on
+// gfx950: one workgroup per (matrix, minor) problem, persistent over a queue.
+//
+// Per problem (the EigenValues step of Algorithms 1 and 2, Section 3 of the
+// paper, applied to A and to each minor M_j of Section 2):
+//   1. gather the minor (row j and column j removed) into a tile-packed lower
+//      triangle in the workgroup's HBM slot;
+//   2. blocked Householder tridiagonalisation Q^T M Q = T (textbook sytrd
+//      form, lower storage): per column an update of the column with the
+//      panel so far, a Householder reflector, and a symmetric matrix-vector
+//      product that streams the stale trailing triangle from HBM once; per
+//      panel of NB columns a rank-2NB update of the trailing triangle on MFMA;
+//   3. all eigenvalues of T by Sturm-count bisection, FP64, one lane per
+//      eigenvalue.
+//
+// Storage of the trailing matrix (type S = double or float): the lower
+// triangle in 64x64 tiles (diagonal tiles hold both triangles).  Tile (I, J),
+// I >= J, is at index J*T - J*(J-1)/2 + (I-J) (tile columns contiguous).  In a
+// tile, element (r, c) sits at (c / VW) * 64 * VW + r * VW + c % VW with
+// VW = 16 / sizeof(S): one 16-byte load gives a lane VW consecutive columns of
+// its row, and 64 lanes cover 1 KiB of contiguous memory.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace eeid {
+
+constexpr int TILE = 64;
+constexpr int TILE_ELEMS = TILE * TILE;
+constexpr int CW = 32;      // columns per SYMV work unit (a half tile)
+constexpr int SEG = 8;      // tiles per SYMV work unit (down a tile column)
+
+struct Item {
+    const double *src;  // matrix (row-major, lda = n)
+    double *out;        // m ascending eigenvalues go here
+    int32_t n;          // order of the source matrix
+    int32_t j;          // deleted row/column, -1 for the matrix itself
+    int32_t m;          // order of the problem (n or n - 1)
+    int32_t b;          // batch index (flags)
+};
+
+template <class S> struct Vec;
+template <> struct Vec<double> { static constexpr int W = 2; typedef double2 type; };
+template <> struct Vec<float> { static constexpr int W = 4; typedef float4 type; };
+
+__device__ __forceinline__ int64_t tile_index(int I, int J, int T) {
+    return (int64_t)J * T - (int64_t)J * (J - 1) / 2 + (I - J);
+}
+
+template <class S>
+__device__ __forceinline__ int tile_off(int r, int c) {
+    constexpr int W = Vec<S>::W;
+    return (c / W) * (TILE * W) + r * W + (c % W);
+}
+
+// One halving step: lanes with bit OFF set keep the upper half of v[0..CNT),
+// the others the lower half, each adding the partner lane's copy of that half.
+template <int CNT, int OFF, int N>
+__device__ __forceinline__ void halve_step(double (&v)[N], int lane) {
+    const bool hi = (lane & OFF) != 0;
+#pragma unroll
+    for (int t = 0; t < CNT / 2; ++t) {
+        const double keep = hi ? v[CNT / 2 + t] : v[t];
+        const double send = hi ? v[t] : v[CNT / 2 + t];
+        v[t] = keep + __shfl_xor(send, OFF);
+    }
+}
+
+// Sum v[0..N) over the 64 lanes of a wave by recursive halving.  Returns the
+// total of column (lane >> (6 - log2 N)); every lane ends with one column.
+template <int N>
+__device__ __forceinline__ double wave_transpose_sum(double (&v)[N], int lane) {
+    static_assert(N == 8 || N == 16 || N == 32, "N");
+    if constexpr (N == 32) halve_step<32, 32>(v, lane);
+    if constexpr (N >= 16) halve_step<16, (N == 32 ? 16 : 32)>(v, lane);
+    halve_step<8, (N == 32 ? 8 : N == 16 ? 16 : 32)>(v, lane);
+    halve_step<4, (N == 32 ? 4 : N == 16 ? 8 : 16)>(v, lane);
+    halve_step<2, (N == 32 ? 2 : N == 16 ? 4 : 8)>(v, lane);
+    double s = v[0];
+    if constexpr (N <= 16) s += __shfl_xor(s, N == 16 ? 2 : 4);
+    if constexpr (N <= 8) s += __shfl_xor(s, 2);
+    s += __shfl_xor(s, 1);
+    return s;
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off);
+    return x;
+}
+__device__ __forceinline__ double wave_min(double x) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x = fmin(x, __shfl_xor(x, off));
+    return x;
+}
+__device__ __forceinline__ double wave_max(double x) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x = fmax(x, __shfl_xor(x, off));
+    return x;
+}
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+// Shared scalars of one problem (lives in LDS).
+template <int NB>
+struct Panel {
+    double tau, alpha2, beta, scal, atb;
+    double a[NB], b[NB];     // a = W^T u, b = V^T u of the latest column
+    double vk[NB], wk[NB];   // row k of V and W for the next column
+    double tmp[2 * NB + 8];
+};
+
+template <class S, int NB, int NT>
+struct Tri {
+    static constexpr int NWAVE = NT / 64;
+
+    // slot pointers
+    S *tiles;
+    double *V, *Wm, *dg, *eg;
+    // LDS
+    double *y, *u, *red;
+    Panel<NB> *P;
+    // problem
+    int m, T, LD;
+    int tid, lane, wave;
+
+    __device__ S *tile_ptr(int I, int J) const { return tiles + tile_index(I, J, T) * TILE_ELEMS; }
+
+    __device__ double Mget(int r, int c) const {  // stored (stale) entry, r >= c region
+        const S *tp = tile_ptr(r / TILE, c / TILE);
+        return (double)tp[tile_off<S>(r % TILE, c % TILE)];
+    }
+
+    // -------------------------------------------------------------- gather
+    __device__ void gather(const Item &it) {
+        const int n = it.n, j = it.j;
+        const double *A = it.src;
+        constexpr int W = Vec<S>::W;
+        for (int J = 0; J < T; ++J)
+            for (int I = J; I < T; ++I) {
+                S *tp = tile_ptr(I, J);
+                for (int q = tid; q < TILE_ELEMS; q += NT) {
+                    const int cp = q / (TILE * W), rem = q % (TILE * W);
+                    const int r = rem / W, c = cp * W + rem % W;
+                    const int row = I * TILE + r, col = J * TILE + c;
+                    double v = 0.0;
+                    if (row < m && col < m) {
+                        const int rs = row + ((j >= 0 && row >= j) ? 1 : 0);
+                        const int cs = col + ((j >= 0 && col >= j) ? 1 : 0);
+                        v = (rs >= cs) ? A[(int64_t)rs * n + cs] : A[(int64_t)cs * n + rs];
+                    }
+                    tp[q] = (S)v;
+                }
+            }
+    }
+
+    // ---------------------------------------------------- column update (pass A)
+    // rows r >= k: finalise W(r, i-1) from the previous column's y, a, b, and
+    // form the updated column x_r = M(r,k) - V(r,:) W(k,:)^T - W(r,:) V(k,:)^T.
+    // Partial sums of |x|^2 and of W^T x, V^T x over rows >= k+2 go to red[].
+    __device__ void column_pass(int k, int i) {
+        const double tau_p = P->tau, a2_p = P->alpha2;
+        double accp = 0.0, accq = 0.0, sig = 0.0;
+        for (int r0 = k; r0 < m; r0 += NT) {
+            // keep the panel scalars in LDS (re-read per row) instead of 4*NB hoisted registers
+            asm volatile("" ::: "memory");
+            const int r = r0 + tid;
+            const bool live = r < m;
+            double vr[NB], wr[NB];
+#pragma unroll
+            for (int l = 0; l < NB; ++l) { vr[l] = 0.0; wr[l] = 0.0; }
+            if (live) {
+#pragma unroll
+                for (int c = 0; c < NB / 8; ++c) {
+                    if (c * 8 < i) {
+#pragma unroll
+                        for (int l = c * 8; l < c * 8 + 8; ++l) {
+                            vr[l] = V[(int64_t)l * LD + r];
+                            wr[l] = Wm[(int64_t)l * LD + r];
+                        }
+                    }
+                }
+            }
+            double x = 0.0;
+            if (live) {
+                if (i > 0) {
+                    double sf = 0.0;
+#pragma unroll
+                    for (int l = 0; l < NB; ++l) sf = fma(vr[l], P->a[l], fma(wr[l], P->b[l], sf));
+                    double vlast = 0.0;
+#pragma unroll
+                    for (int l = 0; l < NB; ++l) vlast = (l == i - 1) ? vr[l] : vlast;
+                    const double wnew = (tau_p != 0.0) ? fma(tau_p, y[r] - sf, a2_p * vlast) : 0.0;
+                    if (r > k) Wm[(int64_t)(i - 1) * LD + r] = wnew;  // row k: written by the previous tail
+#pragma unroll
+                    for (int l = 0; l < NB; ++l) wr[l] = (l == i - 1) ? wnew : wr[l];
+                }
+                double sx = 0.0;
+#pragma unroll
+                for (int l = 0; l < NB; ++l) sx = fma(vr[l], P->wk[l], fma(wr[l], P->vk[l], sx));
+                x = Mget(r, k) - sx;
+                u[r] = x;
+                if (r == k) dg[k] = x;
+            }
+            const double xd = (live && r >= k + 2) ? x : 0.0;
+            sig = fma(xd, xd, sig);
+            if (i > 0) {
+#pragma unroll
+                for (int l = 0; l < NB; ++l) wr[l] *= xd;
+                accp += wave_transpose_sum<NB>(wr, lane);
+#pragma unroll
+                for (int l = 0; l < NB; ++l) vr[l] *= xd;
+                accq += wave_transpose_sum<NB>(vr, lane);
+            }
+        }
+        sig = wave_sum(sig);
+        constexpr int SH = (NB == 32) ? 1 : (NB == 16) ? 2 : 3;
+        if ((lane & ((1 << SH) - 1)) == 0) {
+            const int c = lane >> SH;
+            red[wave * (2 * NB + 8) + c] = accp;
+            red[wave * (2 * NB + 8) + NB + c] = accq;
+        }
+        if (lane == 0) red[wave * (2 * NB + 8) + 2 * NB] = sig;
+    }
+
+    // Finalise W(r, i) for rows r >= r_lo with the current column's y, a, b.
+    __device__ void finalize_pass(int r_lo, int i) {
+        const double tau = P->tau, a2 = P->alpha2;
+        for (int r = r_lo + tid; r < m; r += NT) {
+            double sf = 0.0;
+            for (int l = 0; l < i; ++l)
+                sf = fma(V[(int64_t)l * LD + r], P->a[l], fma(Wm[(int64_t)l * LD + r], P->b[l], sf));
+            const double vl = V[(int64_t)i * LD + r];
+            Wm[(int64_t)i * LD + r] = (tau != 0.0) ? fma(tau, y[r] - sf, a2 * vl) : 0.0;
+        }
+    }
+
+    // ------------------------------------------------------------------- SYMV
+    // y(r) += sum_c M(r, c) u(c) over the stale trailing triangle, each stored
+    // element read once and used twice (row product and column product).
+    __device__ void symv_unit(int J, int h, int Ib, int Ie, int k) {
+        constexpr int W = Vec<S>::W;
+        typedef typename Vec<S>::type VT;
+        const int c0 = J * TILE + h * CW;
+        const double2 *uj2 = reinterpret_cast<const double2 *>(u + c0);  // broadcast LDS reads
+        double pc[CW];
+#pragma unroll
+        for (int c = 0; c < CW; ++c) pc[c] = 0.0;
+        bool any_off = false;
+        for (int I = Ib; I < Ie; ++I) {
+            asm volatile("" ::: "memory");  // u(c0 .. c0+CW) stays in LDS, not in 2*CW registers
+            const S *tp = tile_ptr(I, J) + h * (CW * TILE);
+            const int row = I * TILE + lane;
+            const bool live = row > k;
+            double a[CW];
+            if (live) {
+#pragma unroll
+                for (int q = 0; q < CW / W; ++q) {
+                    const VT v = *reinterpret_cast<const VT *>(tp + q * (TILE * W) + lane * W);
+#pragma unroll
+                    for (int z = 0; z < W; ++z) a[q * W + z] = (double)v[z];
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < CW; ++c) a[c] = 0.0;
+            }
+            double s = 0.0;
+#pragma unroll
+            for (int c = 0; c < CW; c += 2) {
+                const double2 w = uj2[c / 2];
+                s = fma(a[c], w.x, s);
+                s = fma(a[c + 1], w.y, s);
+            }
+            if (I != J) {
+                any_off = true;
+                const double ui = u[row];
+#pragma unroll
+                for (int c = 0; c < CW; ++c) pc[c] = fma(a[c], ui, pc[c]);
+            }
+            if (live) atomicAdd(&y[row], s);
+        }
+        if (any_off) {
+            const double tot = wave_transpose_sum<CW>(pc, lane);
+            if ((lane & 1) == 0) atomicAdd(&y[c0 + (lane >> 1)], tot);
+        }
+    }
+
+    __device__ void symv(int k) {
+        const int J0 = (k + 1) / TILE;
+        int cnt = 0;
+        for (int J = J0; J < T; ++J)
+            for (int h = 0; h < TILE / CW; ++h) {
+                if (J * TILE + h * CW + CW - 1 < k + 1) continue;
+                for (int s0 = J; s0 < T; s0 += SEG) {
+                    if ((cnt++ % NWAVE) == wave) symv_unit(J, h, s0, min(s0 + SEG, T), k);
+                }
+            }
+    }
+
+    // ------------------------------------------------------------------ SYR2K
+    // C(I, J) -= V_I W_J^T + W_I V_J^T for the trailing tiles J >= J1 (MFMA).
+    __device__ void syr2k_tile(int I, int J) {
+        S *tp = tile_ptr(I, J);
+        const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll 1
+        for (int jb = 0; jb < 4; ++jb) {
+            if constexpr (sizeof(S) == 8) {
+                dbl4 acc[4];
+#pragma unroll
+                for (int ib = 0; ib < 4; ++ib) acc[ib] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+                for (int kk = 0; kk < NB; kk += 4) {
+                    const int64_t col = (int64_t)(kk + lk) * LD;
+                    const double aw = Wm[col + J * TILE + jb * 16 + lr];
+                    const double av = V[col + J * TILE + jb * 16 + lr];
+#pragma unroll
+                    for (int ib = 0; ib < 4; ++ib) {
+                        const double bv = V[col + I * TILE + ib * 16 + lr];
+                        const double bw = Wm[col + I * TILE + ib * 16 + lr];
+                        acc[ib] = __builtin_amdgcn_mfma_f64_16x16x4f64(aw, bv, acc[ib], 0, 0, 0);
+                        acc[ib] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bw, acc[ib], 0, 0, 0);
+                    }
+                }
+                // acc[ib][g] = dC(row = ib*16 + lr, col = jb*16 + 4*lk + g)
+#pragma unroll
+                for (int ib = 0; ib < 4; ++ib) {
+                    const int row = ib * 16 + lr, col = jb * 16 + 4 * lk;
+                    double2 *p0 = reinterpret_cast<double2 *>(tp + tile_off<S>(row, col));
+                    double2 *p1 = reinterpret_cast<double2 *>(tp + tile_off<S>(row, col + 2));
+                    double2 c0 = *p0, c1 = *p1;
+                    c0.x -= acc[ib][0]; c0.y -= acc[ib][1];
+                    c1.x -= acc[ib][2]; c1.y -= acc[ib][3];
+                    *p0 = c0; *p1 = c1;
+                }
+            } else {
+                flt4 acc[4];
+#pragma unroll
+                for (int ib = 0; ib < 4; ++ib) acc[ib] = flt4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+                for (int kk = 0; kk < NB; kk += 4) {
+                    const int64_t col = (int64_t)(kk + lk) * LD;
+                    const float aw = (float)Wm[col + J * TILE + jb * 16 + lr];
+                    const float av = (float)V[col + J * TILE + jb * 16 + lr];
+#pragma unroll
+                    for (int ib = 0; ib < 4; ++ib) {
+                        const float bv = (float)V[col + I * TILE + ib * 16 + lr];
+                        const float bw = (float)Wm[col + I * TILE + ib * 16 + lr];
+                        acc[ib] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw, bv, acc[ib], 0, 0, 0);
+                        acc[ib] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bw, acc[ib], 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int ib = 0; ib < 4; ++ib) {
+                    const int row = ib * 16 + lr, col = jb * 16 + 4 * lk;
+                    float4 *p = reinterpret_cast<float4 *>(tp + tile_off<S>(row, col));
+                    float4 c = *p;
+                    c.x -= acc[ib][0]; c.y -= acc[ib][1]; c.z -= acc[ib][2]; c.w -= acc[ib][3];
+                    *p = c;
+                }
+            }
+        }
+    }
+
+    __device__ void syr2k(int J1) {
+        int cnt = 0;
+        for (int J = J1; J < T; ++J)
+            for (int I = J; I < T; ++I)
+                if ((cnt++ % NWAVE) == wave) syr2k_tile(I, J);
+    }
+
+    // --------------------------------------------------------- tridiagonalise
+    __device__ void tridiagonalize() {
+        for (int r = tid; r < LD; r += NT) u[r] = 0.0;
+        if (tid < NB) { P->vk[tid] = 0.0; P->wk[tid] = 0.0; P->a[tid] = 0.0; P->b[tid] = 0.0; }
+        if (tid == 0) { P->tau = 0.0; P->alpha2 = 0.0; }
+        __syncthreads();
+        for (int k0 = 0; k0 < m; k0 += NB) {
+            const int nbe = min(NB, m - k0);
+            {   // clear the panel's V and W from the first tile row the update can touch
+                const int rz = (k0 / TILE) * TILE, len = LD - rz;
+                for (int q = tid; q < NB * len; q += NT) {
+                    const int l = q / len, r = rz + q % len;
+                    V[(int64_t)l * LD + r] = 0.0;
+                    Wm[(int64_t)l * LD + r] = 0.0;
+                }
+            }
+            __syncthreads();
+            for (int i = 0; i < nbe; ++i) {
+                const int k = k0 + i;
+                column_pass(k, i);
+                __syncthreads();
+                if (k == m - 1) break;  // last diagonal entry: no reflector
+                // -------- reflector (wave 0)
+                if (wave == 0) {
+                    // lane l < 2NB: p_l (l < NB) or q_{l-NB}; sigma^2 read by every lane
+                    double s = 0.0, sig = 0.0;
+                    for (int w = 0; w < NWAVE; ++w) {
+                        if (lane < 2 * NB) s += red[w * (2 * NB + 8) + lane];
+                        sig += red[w * (2 * NB + 8) + 2 * NB];
+                    }
+                    const double pl = __shfl(s, lane & (NB - 1));
+                    const double ql = __shfl(s, NB + (lane & (NB - 1)));
+                    const double alpha = u[k + 1];
+                    double beta, tau, scal;
+                    if (sig == 0.0) {
+                        beta = alpha; tau = 0.0; scal = 0.0;
+                    } else {
+                        const double nrm = sqrt(fma(alpha, alpha, sig));
+                        beta = (alpha >= 0.0) ? -nrm : nrm;
+                        tau = (beta - alpha) / beta;
+                        scal = 1.0 / (alpha - beta);
+                    }
+                    double al = 0.0, bl = 0.0;
+                    if (lane < i) {
+                        al = Wm[(int64_t)lane * LD + k + 1] + scal * pl;
+                        bl = V[(int64_t)lane * LD + k + 1] + scal * ql;
+                    }
+                    const double atb = wave_sum(al * bl);
+                    if (lane < NB) { P->a[lane] = al; P->b[lane] = bl; }
+                    if (lane == 0) {
+                        P->tau = tau; P->beta = beta; P->scal = scal; P->atb = atb;
+                        eg[k] = beta;
+                    }
+                }
+                __syncthreads();
+                const double tau = P->tau, scal = P->scal;
+                // -------- u = [0..0, 1, x(k+2:) * scal], V(:, i) = u, y = 0
+                for (int r = k + tid; r < LD; r += NT) {
+                    double v = 0.0;
+                    if (r == k + 1) v = 1.0;
+                    else if (r > k + 1 && r < m) v = u[r] * scal;
+                    u[r] = v;
+                    if (r > k) V[(int64_t)i * LD + r] = v;
+                }
+                for (int r = ((k + 1) / TILE) * TILE + tid; r < LD; r += NT) y[r] = 0.0;
+                __syncthreads();
+                if (tau != 0.0) symv(k);
+                __syncthreads();
+                // -------- alpha2 = -tau^2 (y^T u - 2 a^T b) / 2
+                {
+                    double s = 0.0;
+                    for (int r = k + 1 + tid; r < m; r += NT) s = fma(y[r], u[r], s);
+                    s = wave_sum(s);
+                    if (lane == 0) red[wave * (2 * NB + 8) + 2 * NB + 1] = s;
+                }
+                __syncthreads();
+                if (wave == 0) {
+                    double s = 0.0;
+                    for (int w = 0; w < NWAVE; ++w) s += red[w * (2 * NB + 8) + 2 * NB + 1];
+                    const double a2 = -0.5 * tau * tau * (s - 2.0 * P->atb);
+                    // W(k+1, i) and row k+1 of V, W for the next column
+                    const int kn = k + 1;
+                    double vn = 0.0, wn = 0.0;
+                    if (lane < i) {
+                        vn = V[(int64_t)lane * LD + kn];
+                        wn = Wm[(int64_t)lane * LD + kn];
+                    }
+                    const double sf = wave_sum(lane < i ? fma(vn, P->a[lane], wn * P->b[lane]) : 0.0);
+                    const double wkn = (tau != 0.0) ? fma(tau, y[kn] - sf, a2) : 0.0;
+                    if (lane < NB) {
+                        P->vk[lane] = (lane < i) ? vn : (lane == i ? 1.0 : 0.0);
+                        P->wk[lane] = (lane < i) ? wn : (lane == i ? wkn : 0.0);
+                    }
+                    if (lane == 0) {
+                        P->alpha2 = a2;
+                        Wm[(int64_t)i * LD + kn] = wkn;
+                    }
+                }
+                __syncthreads();
+            }
+            // -------- finish the panel: last W column, then the trailing update
+            const int klast = k0 + nbe - 1;
+            if (klast < m - 1) {
+                finalize_pass(klast + 2, nbe - 1);
+                __syncthreads();
+                const int J1 = (k0 + nbe) / TILE;
+                syr2k(J1);
+                __syncthreads();
+                if (tid < NB) { P->vk[tid] = 0.0; P->wk[tid] = 0.0; }
+                __syncthreads();
+            }
+        }
+    }
+
+    // ------------------------------------------------------------- bisection
+    // All eigenvalues of the symmetric tridiagonal (dg, eg) ascending, by
+    // Sturm counts: count(x) = #{i : q_i < 0}, q_0 = d_0 - x,
+    // q_i = d_i - x - e_{i-1}^2 / q_{i-1}, tiny pivots replaced by -pivmin.
+    __device__ void bisect(double *out) {
+        double *de = y;  // reuse: de[2i] = d_i, de[2i+1] = e_{i-1}^2
+        double gl = 1e308, gu = -1e308, emax2 = 0.0;
+        for (int i = tid; i < m; i += NT) {
+            const double d = dg[i];
+            const double el = (i > 0) ? fabs(eg[i - 1]) : 0.0;
+            const double er = (i < m - 1) ? fabs(eg[i]) : 0.0;
+            de[2 * i] = d;
+            de[2 * i + 1] = el * el;
+            gl = fmin(gl, d - el - er);
+            gu = fmax(gu, d + el + er);
+            emax2 = fmax(emax2, el * el);
+        }
+        gl = wave_min(gl); gu = wave_max(gu); emax2 = wave_max(emax2);
+        if (lane == 0) {
+            red[wave * 4 + 0] = gl; red[wave * 4 + 1] = gu; red[wave * 4 + 2] = emax2;
+        }
+        __syncthreads();
+        gl = 1e308; gu = -1e308; emax2 = 0.0;
+        for (int w = 0; w < NWAVE; ++w) {
+            gl = fmin(gl, red[w * 4]); gu = fmax(gu, red[w * 4 + 1]); emax2 = fmax(emax2, red[w * 4 + 2]);
+        }
+        const double eps = 2.220446049250313e-16;
+        const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
+        const double tnorm = fmax(fabs(gl), fabs(gu));
+        const double pad = 2.0 * eps * tnorm * (double)m + 4.0 * pivmin;
+        gl -= pad; gu += pad;
+        const double atol = eps * tnorm;
+        constexpr int ILP = 4;
+        for (int base = 0; base < m; base += NT * ILP) {
+            double lo[ILP], hi[ILP];
+            int idx[ILP];
+            bool done[ILP];
+#pragma unroll
+            for (int t = 0; t < ILP; ++t) {
+                idx[t] = base + t * NT + tid;
+                lo[t] = gl; hi[t] = gu;
+                done[t] = idx[t] >= m;
+            }
+            for (int it = 0; it < 80; ++it) {
+                bool all = true;
+#pragma unroll
+                for (int t = 0; t < ILP; ++t) all = all && done[t];
+                if (all) break;
+                double x[ILP], q[ILP];
+                int cnt[ILP];
+#pragma unroll
+                for (int t = 0; t < ILP; ++t) { x[t] = 0.5 * (lo[t] + hi[t]); q[t] = 1.0; cnt[t] = 0; }
+                for (int i = 0; i < m; ++i) {
+                    const double d = de[2 * i], e2 = de[2 * i + 1];
+#pragma unroll
+                    for (int t = 0; t < ILP; ++t) {
+                        double v = (d - x[t]) - e2 / q[t];
+                        v = (fabs(v) < pivmin) ? -pivmin : v;
+                        cnt[t] += (v < 0.0) ? 1 : 0;
+                        q[t] = v;
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < ILP; ++t) {
+                    if (done[t]) continue;
+                    if (cnt[t] > idx[t]) hi[t] = x[t]; else lo[t] = x[t];
+                    const double w = hi[t] - lo[t];
+                    const double mid = 0.5 * (lo[t] + hi[t]);
+                    if (w <= fmax(2.0 * eps * fmax(fabs(lo[t]), fabs(hi[t])), atol) || mid <= lo[t] || mid >= hi[t])
+                        done[t] = true;
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < ILP; ++t)
+                if (idx[t] < m) out[idx[t]] = 0.5 * (lo[t] + hi[t]);
+        }
+    }
+};
+
+struct TriArgs {
+    const Item *items;
+    int64_t n_items;
+    int *counter;
+    const int32_t *flags;
+    char *work;
+    int64_t slot_bytes;
+    int LDmax;
+};
+
+template <class S, int NB>
+__host__ __device__ inline int64_t slot_bytes_for(int LDmax) {
+    const int64_t T = LDmax / TILE;
+    const int64_t tiles = T * (T + 1) / 2 * TILE_ELEMS * (int64_t)sizeof(S);
+    const int64_t panel = 2 * (int64_t)NB * LDmax * 8;
+    const int64_t de = 2 * (int64_t)LDmax * 8;
+    return ((tiles + 255) / 256) * 256 + panel + de;
+}
+
+template <int NB, int NT>
+__host__ __device__ inline int64_t lds_bytes_for(int LDmax) {
+    return (2 * (int64_t)LDmax + (NT / 64) * (2 * NB + 8)) * 8 + (int64_t)sizeof(Panel<NB>) + 64;
+}
+
+template <class S, int NB, int NT>
+__global__ __launch_bounds__(NT) void tridiag_bisect_kernel(TriArgs args) {
+    extern __shared__ double lds[];
+    __shared__ int s_item;
+    Tri<S, NB, NT> t;
+    t.tid = threadIdx.x;
+    t.lane = threadIdx.x & 63;
+    t.wave = threadIdx.x >> 6;
+    const int LDmax = args.LDmax;
+    t.y = lds;
+    t.u = lds + LDmax;
+    t.red = lds + 2 * LDmax;
+    t.P = reinterpret_cast<Panel<NB> *>(t.red + (NT / 64) * (2 * NB + 8));
+    char *slot = args.work + (int64_t)blockIdx.x * args.slot_bytes;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(args.counter, 1);
+        __syncthreads();
+        const int64_t it_idx = s_item;
+        __syncthreads();
+        if (it_idx >= args.n_items) break;
+        const Item it = args.items[it_idx];
+        if (args.flags[it.b] & 1) {  // non-finite input: NaN out
+            for (int i = threadIdx.x; i < it.m; i += NT) it.out[i] = __builtin_nan("");
+            continue;
+        }
+        t.m = it.m;
+        t.T = (it.m + TILE - 1) / TILE;
+        t.LD = t.T * TILE;
+        t.tiles = reinterpret_cast<S *>(slot);
+        const int64_t T = t.T;
+        const int64_t tile_bytes = ((T * (T + 1) / 2 * TILE_ELEMS * (int64_t)sizeof(S) + 255) / 256) * 256;
+        t.V = reinterpret_cast<double *>(slot + tile_bytes);
+        t.Wm = t.V + (int64_t)NB * t.LD;
+        t.dg = t.Wm + (int64_t)NB * t.LD;
+        t.eg = t.dg + t.LD;
+        t.gather(it);
+        __syncthreads();
+        t.tridiagonalize();
+        __syncthreads();
+        t.bisect(it.out);
+        __syncthreads();
+    }
+}
+
+}  // namespace eeid
