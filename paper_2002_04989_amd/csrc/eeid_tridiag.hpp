@@ -322,16 +322,13 @@ struct Tri {
                         acc[ib] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bw, acc[ib], 0, 0, 0);
                     }
                 }
-                // acc[ib][g] = dC(row = ib*16 + lr, col = jb*16 + 4*lk + g)
+                // The f64 16x16x4 result holds element (lk + 4g, lr) of the block in
+                // lane (lr + 16 lk), register g: acc[ib][g] = dC(ib*16 + lr, jb*16 + lk + 4g).
 #pragma unroll
                 for (int ib = 0; ib < 4; ++ib) {
-                    const int row = ib * 16 + lr, col = jb * 16 + 4 * lk;
-                    double2 *p0 = reinterpret_cast<double2 *>(tp + tile_off<S>(row, col));
-                    double2 *p1 = reinterpret_cast<double2 *>(tp + tile_off<S>(row, col + 2));
-                    double2 c0 = *p0, c1 = *p1;
-                    c0.x -= acc[ib][0]; c0.y -= acc[ib][1];
-                    c1.x -= acc[ib][2]; c1.y -= acc[ib][3];
-                    *p0 = c0; *p1 = c1;
+                    const int row = ib * 16 + lr;
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) tp[tile_off<S>(row, jb * 16 + lk + 4 * g)] -= acc[ib][g];
                 }
             } else {
                 flt4 acc[4];
@@ -350,6 +347,8 @@ struct Tri {
                         acc[ib] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bw, acc[ib], 0, 0, 0);
                     }
                 }
+                // The f32 16x16x4 result holds element (4 lk + g, lr) of the block in
+                // lane (lr + 16 lk), register g: acc[ib][g] = dC(ib*16 + lr, jb*16 + 4 lk + g).
 #pragma unroll
                 for (int ib = 0; ib < 4; ++ib) {
                     const int row = ib * 16 + lr, col = jb * 16 + 4 * lk;
