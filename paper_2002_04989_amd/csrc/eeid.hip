@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -20,7 +21,6 @@
 namespace {
 
 constexpr int NB = 32;   // panel width of the blocked tridiagonalisation
-constexpr int NT = 512;  // threads per problem workgroup
 
 struct Buf {
     void *p = nullptr;
@@ -38,6 +38,7 @@ struct eeid_handle_s {
     int *counter = nullptr;
     std::vector<int64_t> items_key, desc_key;
     int64_t n_items = 0;
+    int wg_threads = 512;  // threads per problem workgroup: 512 or 256
 };
 
 namespace {
@@ -118,7 +119,7 @@ eeid_status_t upload_desc(eeid_handle_t h, int64_t count, const int64_t *n, cons
     return EEID_OK;
 }
 
-template <class S>
+template <class S, int NT>
 eeid_status_t launch_tridiag(eeid_handle_t h, const std::vector<eeid::Item> &items,
                              const std::vector<int64_t> &key, int max_m, const int32_t *flags) {
     using namespace eeid;
@@ -207,8 +208,12 @@ eeid_status_t run_eigs(eeid_handle_t h, eeid_prec_t p, int64_t count, const int6
     hipLaunchKernelGGL(eeid::nonfinite_kernel, dim3((unsigned)nn_blocks, (unsigned)count), dim3(256), 0,
                        h->stream, desc, Ad, 0, flags);
     HIP_TRY(h, hipGetLastError());
-    if (p == EEID_PREC_FP64) return launch_tridiag<double>(h, items, key, (int)nmax, flags);
-    return launch_tridiag<float>(h, items, key, (int)nmax, flags);
+    const bool wide = h->wg_threads == 512;
+    if (p == EEID_PREC_FP64)
+        return wide ? launch_tridiag<double, 512>(h, items, key, (int)nmax, flags)
+                    : launch_tridiag<double, 256>(h, items, key, (int)nmax, flags);
+    return wide ? launch_tridiag<float, 512>(h, items, key, (int)nmax, flags)
+                : launch_tridiag<float, 256>(h, items, key, (int)nmax, flags);
 }
 
 }  // namespace
@@ -227,6 +232,7 @@ eeid_status_t eeid_create(eeid_handle_t *out, int hip_device) {
     eeid_handle_t h = new (std::nothrow) eeid_handle_s();
     if (!h) return EEID_ERR_ALLOC;
     h->device = hip_device;
+    if (const char *e = getenv("EEID_WG_THREADS")) h->wg_threads = (atoi(e) == 256) ? 256 : 512;
     if (hipSetDevice(hip_device) != hipSuccess ||
         hipDeviceGetAttribute(&h->cu_count, hipDeviceAttributeMultiprocessorCount, hip_device) != hipSuccess ||
         hipMalloc(&h->counter, sizeof(int)) != hipSuccess) {

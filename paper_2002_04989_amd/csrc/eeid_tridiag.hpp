@@ -300,62 +300,96 @@ struct Tri {
 
     // ------------------------------------------------------------------ SYR2K
     // C(I, J) -= V_I W_J^T + W_I V_J^T for the trailing tiles J >= J1 (MFMA).
+    // All sixteen 16x16 blocks of the tile accumulate at once (independent
+    // MFMA chains); the panel columns are consumed four at a time.
     __device__ void syr2k_tile(int I, int J) {
         S *tp = tile_ptr(I, J);
         const int lr = lane & 15, lk = lane >> 4;
+        const double *vJ = V + J * TILE + lr, *wJ = Wm + J * TILE + lr;
+        const double *vI = V + I * TILE + lr, *wI = Wm + I * TILE + lr;
+        if constexpr (sizeof(S) == 8) {
+            // two column blocks at a time: 8 accumulators (64 registers) per pass
 #pragma unroll 1
-        for (int jb = 0; jb < 4; ++jb) {
-            if constexpr (sizeof(S) == 8) {
-                dbl4 acc[4];
+            for (int jp = 0; jp < 4; jp += 2) {
+                dbl4 acc[2][4];  // [jb - jp][ib]
 #pragma unroll
-                for (int ib = 0; ib < 4; ++ib) acc[ib] = dbl4{0.0, 0.0, 0.0, 0.0};
+                for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+                    for (int ib = 0; ib < 4; ++ib) acc[jb][ib] = dbl4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 2
                 for (int kk = 0; kk < NB; kk += 4) {
                     const int64_t col = (int64_t)(kk + lk) * LD;
-                    const double aw = Wm[col + J * TILE + jb * 16 + lr];
-                    const double av = V[col + J * TILE + jb * 16 + lr];
+                    double aw[2], av[2], bv[4], bw[4];
 #pragma unroll
-                    for (int ib = 0; ib < 4; ++ib) {
-                        const double bv = V[col + I * TILE + ib * 16 + lr];
-                        const double bw = Wm[col + I * TILE + ib * 16 + lr];
-                        acc[ib] = __builtin_amdgcn_mfma_f64_16x16x4f64(aw, bv, acc[ib], 0, 0, 0);
-                        acc[ib] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bw, acc[ib], 0, 0, 0);
+                    for (int q = 0; q < 2; ++q) {
+                        aw[q] = wJ[col + (jp + q) * 16];
+                        av[q] = vJ[col + (jp + q) * 16];
                     }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) { bv[q] = vI[col + q * 16]; bw[q] = wI[col + q * 16]; }
+#pragma unroll
+                    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+                        for (int ib = 0; ib < 4; ++ib)
+                            acc[jb][ib] = __builtin_amdgcn_mfma_f64_16x16x4f64(aw[jb], bv[ib], acc[jb][ib], 0, 0, 0);
+#pragma unroll
+                    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+                        for (int ib = 0; ib < 4; ++ib)
+                            acc[jb][ib] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[jb], bw[ib], acc[jb][ib], 0, 0, 0);
                 }
                 // The f64 16x16x4 result holds element (lk + 4g, lr) of the block in
-                // lane (lr + 16 lk), register g: acc[ib][g] = dC(ib*16 + lr, jb*16 + lk + 4g).
+                // lane (lr + 16 lk), register g: acc[jb][ib][g] = dC(ib*16 + lr, jb*16 + lk + 4g).
 #pragma unroll
-                for (int ib = 0; ib < 4; ++ib) {
-                    const int row = ib * 16 + lr;
+                for (int jb = 0; jb < 2; ++jb) {
+                    const int c0 = (jp + jb) * 16 + lk;
+                    double c[4][4];
 #pragma unroll
-                    for (int g = 0; g < 4; ++g) tp[tile_off<S>(row, jb * 16 + lk + 4 * g)] -= acc[ib][g];
+                    for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+                        for (int g = 0; g < 4; ++g) c[ib][g] = tp[tile_off<S>(ib * 16 + lr, c0 + 4 * g)];
+#pragma unroll
+                    for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+                        for (int g = 0; g < 4; ++g) tp[tile_off<S>(ib * 16 + lr, c0 + 4 * g)] = c[ib][g] - acc[jb][ib][g];
                 }
-            } else {
-                flt4 acc[4];
+            }
+        } else {
+            flt4 acc[4][4];
 #pragma unroll
-                for (int ib = 0; ib < 4; ++ib) acc[ib] = flt4{0.f, 0.f, 0.f, 0.f};
+            for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+                for (int ib = 0; ib < 4; ++ib) acc[jb][ib] = flt4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 2
-                for (int kk = 0; kk < NB; kk += 4) {
-                    const int64_t col = (int64_t)(kk + lk) * LD;
-                    const float aw = (float)Wm[col + J * TILE + jb * 16 + lr];
-                    const float av = (float)V[col + J * TILE + jb * 16 + lr];
+            for (int kk = 0; kk < NB; kk += 4) {
+                const int64_t col = (int64_t)(kk + lk) * LD;
+                float aw[4], av[4], bv[4], bw[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    aw[q] = (float)wJ[col + q * 16]; av[q] = (float)vJ[col + q * 16];
+                    bv[q] = (float)vI[col + q * 16]; bw[q] = (float)wI[col + q * 16];
+                }
+#pragma unroll
+                for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
                     for (int ib = 0; ib < 4; ++ib) {
-                        const float bv = (float)V[col + I * TILE + ib * 16 + lr];
-                        const float bw = (float)Wm[col + I * TILE + ib * 16 + lr];
-                        acc[ib] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw, bv, acc[ib], 0, 0, 0);
-                        acc[ib] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bw, acc[ib], 0, 0, 0);
+                        acc[jb][ib] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw[jb], bv[ib], acc[jb][ib], 0, 0, 0);
+                        acc[jb][ib] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[jb], bw[ib], acc[jb][ib], 0, 0, 0);
                     }
-                }
-                // The f32 16x16x4 result holds element (4 lk + g, lr) of the block in
-                // lane (lr + 16 lk), register g: acc[ib][g] = dC(ib*16 + lr, jb*16 + 4 lk + g).
+            }
+            // The f32 16x16x4 result holds element (4 lk + g, lr) of the block in
+            // lane (lr + 16 lk), register g: acc[jb][ib][g] = dC(ib*16 + lr, jb*16 + 4 lk + g).
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb) {
+                float4 c[4];
+#pragma unroll
+                for (int ib = 0; ib < 4; ++ib)
+                    c[ib] = *reinterpret_cast<const float4 *>(tp + tile_off<S>(ib * 16 + lr, jb * 16 + 4 * lk));
 #pragma unroll
                 for (int ib = 0; ib < 4; ++ib) {
-                    const int row = ib * 16 + lr, col = jb * 16 + 4 * lk;
-                    float4 *p = reinterpret_cast<float4 *>(tp + tile_off<S>(row, col));
-                    float4 c = *p;
-                    c.x -= acc[ib][0]; c.y -= acc[ib][1]; c.z -= acc[ib][2]; c.w -= acc[ib][3];
-                    *p = c;
+                    c[ib].x -= acc[jb][ib][0]; c[ib].y -= acc[jb][ib][1];
+                    c[ib].z -= acc[jb][ib][2]; c[ib].w -= acc[jb][ib][3];
+                    *reinterpret_cast<float4 *>(tp + tile_off<S>(ib * 16 + lr, jb * 16 + 4 * lk)) = c[ib];
                 }
             }
         }
@@ -585,8 +619,11 @@ __host__ __device__ inline int64_t lds_bytes_for(int LDmax) {
     return (2 * (int64_t)LDmax + (NT / 64) * (2 * NB + 8)) * 8 + (int64_t)sizeof(Panel<NB>) + 64;
 }
 
+// NT = 512: one problem per CU (8 waves).  NT = 256: two problems per CU, so
+// that the latency-bound phases of one overlap the HBM stream of the other;
+// at least two waves per SIMD caps the kernel at 256 registers either way.
 template <class S, int NB, int NT>
-__global__ __launch_bounds__(NT) void tridiag_bisect_kernel(TriArgs args) {
+__global__ __launch_bounds__(NT, 2) void tridiag_bisect_kernel(TriArgs args) {
     extern __shared__ double lds[];
     __shared__ int s_item;
     Tri<S, NB, NT> t;
