@@ -20,7 +20,6 @@
 
 namespace {
 
-constexpr int NB = 32;   // panel width of the blocked tridiagonalisation
 
 struct Buf {
     void *p = nullptr;
@@ -38,7 +37,7 @@ struct eeid_handle_s {
     int *counter = nullptr;
     std::vector<int64_t> items_key, desc_key;
     int64_t n_items = 0;
-    int wg_threads = 512;  // threads per problem workgroup: 512 or 256
+    int variant = 0;  // kernel configuration (dispatch_variant)
 };
 
 namespace {
@@ -119,7 +118,8 @@ eeid_status_t upload_desc(eeid_handle_t h, int64_t count, const int64_t *n, cons
     return EEID_OK;
 }
 
-template <class S, int NT>
+// One compiled configuration of the tridiagonalisation kernel.
+template <class S, int NB, int NT, int CW, bool STAGE, int WPE>
 eeid_status_t launch_tridiag(eeid_handle_t h, const std::vector<eeid::Item> &items,
                              const std::vector<int64_t> &key, int max_m, const int32_t *flags) {
     using namespace eeid;
@@ -134,8 +134,8 @@ eeid_status_t launch_tridiag(eeid_handle_t h, const std::vector<eeid::Item> &ite
     }
     const int LDmax = ((max_m + TILE - 1) / TILE) * TILE;
     const int64_t slot = slot_bytes_for<S, NB>(LDmax);
-    const size_t lds = (size_t)lds_bytes_for<NB, NT>(LDmax);
-    auto kern = tridiag_bisect_kernel<S, NB, NT>;
+    const size_t lds = (size_t)lds_bytes_for<NB, NT, STAGE>(LDmax);
+    auto kern = tridiag_bisect_kernel<S, NB, NT, CW, STAGE, WPE>;
     HIP_TRY(h, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int per_cu = 0;
     HIP_TRY(h, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, lds));
@@ -161,6 +161,21 @@ eeid_status_t launch_tridiag(eeid_handle_t h, const std::vector<eeid::Item> &ite
     hipLaunchKernelGGL(kern, dim3((unsigned)slots), dim3(NT), lds, h->stream, a);
     HIP_TRY(h, hipGetLastError());
     return EEID_OK;
+}
+
+// Kernel configurations: (panel width NB, threads NT, SYMV unit width CW,
+// LDS staging of the trailing update, waves per SIMD).
+eeid_status_t dispatch_variant(eeid_handle_t h, eeid_prec_t p, const std::vector<eeid::Item> &items,
+                               const std::vector<int64_t> &key, int nmax, const int32_t *flags) {
+    const bool d = (p == EEID_PREC_FP64);
+    switch (h->variant) {
+        case 1:
+            return d ? launch_tridiag<double, 32, 256, 32, true, 2>(h, items, key, nmax, flags)
+                     : launch_tridiag<float, 32, 256, 32, true, 2>(h, items, key, nmax, flags);
+        default:
+            return d ? launch_tridiag<double, 32, 512, 32, true, 2>(h, items, key, nmax, flags)
+                     : launch_tridiag<float, 32, 512, 32, true, 2>(h, items, key, nmax, flags);
+    }
 }
 
 // kind 0: eigenvalues of the matrices only; kind 1: matrices and all minors;
@@ -208,12 +223,7 @@ eeid_status_t run_eigs(eeid_handle_t h, eeid_prec_t p, int64_t count, const int6
     hipLaunchKernelGGL(eeid::nonfinite_kernel, dim3((unsigned)nn_blocks, (unsigned)count), dim3(256), 0,
                        h->stream, desc, Ad, 0, flags);
     HIP_TRY(h, hipGetLastError());
-    const bool wide = h->wg_threads == 512;
-    if (p == EEID_PREC_FP64)
-        return wide ? launch_tridiag<double, 512>(h, items, key, (int)nmax, flags)
-                    : launch_tridiag<double, 256>(h, items, key, (int)nmax, flags);
-    return wide ? launch_tridiag<float, 512>(h, items, key, (int)nmax, flags)
-                : launch_tridiag<float, 256>(h, items, key, (int)nmax, flags);
+    return dispatch_variant(h, p, items, key, (int)nmax, flags);
 }
 
 }  // namespace
@@ -232,7 +242,7 @@ eeid_status_t eeid_create(eeid_handle_t *out, int hip_device) {
     eeid_handle_t h = new (std::nothrow) eeid_handle_s();
     if (!h) return EEID_ERR_ALLOC;
     h->device = hip_device;
-    if (const char *e = getenv("EEID_WG_THREADS")) h->wg_threads = (atoi(e) == 256) ? 256 : 512;
+    if (const char *e = getenv("EEID_VARIANT")) h->variant = atoi(e);
     if (hipSetDevice(hip_device) != hipSuccess ||
         hipDeviceGetAttribute(&h->cu_count, hipDeviceAttributeMultiprocessorCount, hip_device) != hipSuccess ||
         hipMalloc(&h->counter, sizeof(int)) != hipSuccess) {

@@ -27,7 +27,6 @@ namespace eeid {
 
 constexpr int TILE = 64;
 constexpr int TILE_ELEMS = TILE * TILE;
-constexpr int CW = 32;      // columns per SYMV work unit (a half tile)
 constexpr int SEG = 8;      // tiles per SYMV work unit (down a tile column)
 
 struct Item {
@@ -111,7 +110,11 @@ struct Panel {
     double tmp[2 * NB + 8];
 };
 
-template <class S, int NB, int NT>
+// S: storage type of the trailing matrix; NB: panel width; NT: threads per
+// workgroup; CW: columns per SYMV work unit (32 or 16); STAGE: stage the
+// trailing update's J-side panel rows in LDS; BILP: eigenvalues bisected
+// together per lane.
+template <class S, int NB, int NT, int CW, bool STAGE, int BILP>
 struct Tri {
     static constexpr int NWAVE = NT / 64;
 
@@ -119,7 +122,7 @@ struct Tri {
     S *tiles;
     double *V, *Wm, *dg, *eg;
     // LDS
-    double *y, *u, *red;
+    double *y, *u, *red, *stage;  // stage: 2 * NB * 64 doubles for the trailing update
     Panel<NB> *P;
     // problem
     int m, T, LD;
@@ -171,6 +174,7 @@ struct Tri {
 #pragma unroll
             for (int l = 0; l < NB; ++l) { vr[l] = 0.0; wr[l] = 0.0; }
             if (live) {
+                // columns l >= i of the panel are still zero; whole chunks past i are skipped
 #pragma unroll
                 for (int c = 0; c < NB / 8; ++c) {
                     if (c * 8 < i) {
@@ -238,168 +242,218 @@ struct Tri {
 
     // ------------------------------------------------------------------- SYMV
     // y(r) += sum_c M(r, c) u(c) over the stale trailing triangle, each stored
-    // element read once and used twice (row product and column product).
+    // element read once and used twice (row product and column product).  A
+    // unit is CW columns of tile column J over tile rows [Ib, Ie); lane = row.
+    typedef typename Vec<S>::type VT;
+    static constexpr int VW = Vec<S>::W;
+    static constexpr int NV = CW / VW;  // 16-byte vectors per lane per tile
+
     __device__ void symv_unit(int J, int h, int Ib, int Ie, int k) {
-        constexpr int W = Vec<S>::W;
-        typedef typename Vec<S>::type VT;
         const int c0 = J * TILE + h * CW;
-        const double2 *uj2 = reinterpret_cast<const double2 *>(u + c0);  // broadcast LDS reads
+        // Columns left of the trailing matrix are loaded too (one base address,
+        // immediate offsets, all loads in flight together): they meet u = 0 in
+        // the row product, and their column sums land in entries of y that are
+        // never read.
         double pc[CW];
 #pragma unroll
         for (int c = 0; c < CW; ++c) pc[c] = 0.0;
-        bool any_off = false;
         for (int I = Ib; I < Ie; ++I) {
-            asm volatile("" ::: "memory");  // u(c0 .. c0+CW) stays in LDS, not in 2*CW registers
+            int uo = c0;
+            asm volatile("" : "+v"(uo));  // u(c0 .. c0+CW) is re-read from LDS, not held in registers
+            const double2 *uj2 = reinterpret_cast<const double2 *>(u + uo);
             const S *tp = tile_ptr(I, J) + h * (CW * TILE);
             const int row = I * TILE + lane;
             const bool live = row > k;
-            double a[CW];
+            VT buf[NV];
             if (live) {
 #pragma unroll
-                for (int q = 0; q < CW / W; ++q) {
-                    const VT v = *reinterpret_cast<const VT *>(tp + q * (TILE * W) + lane * W);
-#pragma unroll
-                    for (int z = 0; z < W; ++z) a[q * W + z] = (double)v[z];
-                }
+                for (int q = 0; q < NV; ++q) buf[q] = *reinterpret_cast<const VT *>(tp + q * (TILE * VW) + lane * VW);
             } else {
 #pragma unroll
-                for (int c = 0; c < CW; ++c) a[c] = 0.0;
+                for (int q = 0; q < NV; ++q) buf[q] = VT{};
             }
             double s = 0.0;
 #pragma unroll
-            for (int c = 0; c < CW; c += 2) {
-                const double2 w = uj2[c / 2];
-                s = fma(a[c], w.x, s);
-                s = fma(a[c + 1], w.y, s);
-            }
+            for (int q = 0; q < NV; ++q)
+#pragma unroll
+                for (int z = 0; z < VW; z += 2) {
+                    const double2 w = uj2[(q * VW + z) / 2];
+                    s = fma((double)buf[q][z], w.x, s);
+                    s = fma((double)buf[q][z + 1], w.y, s);
+                }
             if (I != J) {
-                any_off = true;
                 const double ui = u[row];
 #pragma unroll
-                for (int c = 0; c < CW; ++c) pc[c] = fma(a[c], ui, pc[c]);
+                for (int q = 0; q < NV; ++q)
+#pragma unroll
+                    for (int z = 0; z < VW; ++z) pc[q * VW + z] = fma((double)buf[q][z], ui, pc[q * VW + z]);
             }
             if (live) atomicAdd(&y[row], s);
         }
-        if (any_off) {
+        if (Ie > Ib + (Ib == J ? 1 : 0)) {  // some off-diagonal tile contributed column sums
+            constexpr int SH = (CW == 32) ? 1 : 2;
             const double tot = wave_transpose_sum<CW>(pc, lane);
-            if ((lane & 1) == 0) atomicAdd(&y[c0 + (lane >> 1)], tot);
+            if ((lane & ((1 << SH) - 1)) == 0) atomicAdd(&y[c0 + (lane >> SH)], tot);
         }
     }
 
+    // Work units (tile column J, half h, run of up to SEG tiles down the column)
+    // are dealt to the waves longest first in snake order (0..7, 7..0, ...),
+    // which keeps the waves within a few percent of each other.
     __device__ void symv(int k) {
         const int J0 = (k + 1) / TILE;
         int cnt = 0;
+        auto take = [&](int J, int h, int Ib, int Ie) {
+            const int r = cnt / NWAVE, c = cnt % NWAVE;
+            const int w = (r & 1) ? (NWAVE - 1 - c) : c;
+            ++cnt;
+            if (w == wave) symv_unit(J, h, Ib, Ie, k);
+        };
+        // full-length runs
         for (int J = J0; J < T; ++J)
             for (int h = 0; h < TILE / CW; ++h) {
                 if (J * TILE + h * CW + CW - 1 < k + 1) continue;
-                for (int s0 = J; s0 < T; s0 += SEG) {
-                    if ((cnt++ % NWAVE) == wave) symv_unit(J, h, s0, min(s0 + SEG, T), k);
-                }
+                for (int s0 = J; s0 + SEG <= T; s0 += SEG) take(J, h, s0, s0 + SEG);
             }
+        // the shorter tail runs, longest first
+        for (int L = SEG - 1; L >= 1; --L)
+            for (int J = T - L; J >= J0; J -= SEG)
+                for (int h = 0; h < TILE / CW; ++h) {
+                    if (J * TILE + h * CW + CW - 1 < k + 1) continue;
+                    take(J, h, T - L, T);
+                }
     }
 
     // ------------------------------------------------------------------ SYR2K
     // C(I, J) -= V_I W_J^T + W_I V_J^T for the trailing tiles J >= J1 (MFMA).
-    // All sixteen 16x16 blocks of the tile accumulate at once (independent
-    // MFMA chains); the panel columns are consumed four at a time.
-    __device__ void syr2k_tile(int I, int J) {
+    // C(I, J) -= V_I W_J^T + W_I V_J^T on MFMA.  The J-side panel rows (V_J,
+    // W_J) come from LDS (staged once per tile column for all waves, column k
+    // of the panel at vs[k*64 + row]); the I-side rows are loaded from the slot
+    // once per tile.  Two passes of two 16-row blocks keep 8 accumulators live.
+    // SLD = TILE: vs/ws are the LDS copies (column k at vs[k*64 + row]);
+    // SLD = 0: vs/ws point at row J*64 of the slot's V/W (column k at k*LD).
+    template <int SLD>
+    __device__ void syr2k_tile(int I, int J, const double *vs, const double *ws) {
         S *tp = tile_ptr(I, J);
         const int lr = lane & 15, lk = lane >> 4;
-        const double *vJ = V + J * TILE + lr, *wJ = Wm + J * TILE + lr;
         const double *vI = V + I * TILE + lr, *wI = Wm + I * TILE + lr;
-        if constexpr (sizeof(S) == 8) {
-            // two column blocks at a time: 8 accumulators (64 registers) per pass
 #pragma unroll 1
-            for (int jp = 0; jp < 4; jp += 2) {
-                dbl4 acc[2][4];  // [jb - jp][ib]
+        for (int ip = 0; ip < 4; ip += 2) {
+            if constexpr (sizeof(S) == 8) {
+                dbl4 acc[4][2];  // [jb][ib - ip]
 #pragma unroll
-                for (int jb = 0; jb < 2; ++jb)
+                for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
-                    for (int ib = 0; ib < 4; ++ib) acc[jb][ib] = dbl4{0.0, 0.0, 0.0, 0.0};
+                    for (int ib = 0; ib < 2; ++ib) acc[jb][ib] = dbl4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 2
                 for (int kk = 0; kk < NB; kk += 4) {
                     const int64_t col = (int64_t)(kk + lk) * LD;
-                    double aw[2], av[2], bv[4], bw[4];
+                    const int64_t sc = (int64_t)(kk + lk) * (SLD ? SLD : LD) + lr;
+                    double aw[4], av[4], bv[2], bw[2];
 #pragma unroll
                     for (int q = 0; q < 2; ++q) {
-                        aw[q] = wJ[col + (jp + q) * 16];
-                        av[q] = vJ[col + (jp + q) * 16];
+                        bv[q] = vI[col + (ip + q) * 16];
+                        bw[q] = wI[col + (ip + q) * 16];
                     }
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) { bv[q] = vI[col + q * 16]; bw[q] = wI[col + q * 16]; }
+                    for (int q = 0; q < 4; ++q) { aw[q] = ws[sc + q * 16]; av[q] = vs[sc + q * 16]; }
 #pragma unroll
-                    for (int jb = 0; jb < 2; ++jb)
+                    for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
-                        for (int ib = 0; ib < 4; ++ib)
+                        for (int ib = 0; ib < 2; ++ib)
                             acc[jb][ib] = __builtin_amdgcn_mfma_f64_16x16x4f64(aw[jb], bv[ib], acc[jb][ib], 0, 0, 0);
 #pragma unroll
-                    for (int jb = 0; jb < 2; ++jb)
+                    for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
-                        for (int ib = 0; ib < 4; ++ib)
+                        for (int ib = 0; ib < 2; ++ib)
                             acc[jb][ib] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[jb], bw[ib], acc[jb][ib], 0, 0, 0);
                 }
                 // The f64 16x16x4 result holds element (lk + 4g, lr) of the block in
                 // lane (lr + 16 lk), register g: acc[jb][ib][g] = dC(ib*16 + lr, jb*16 + lk + 4g).
 #pragma unroll
-                for (int jb = 0; jb < 2; ++jb) {
-                    const int c0 = (jp + jb) * 16 + lk;
+                for (int ib = 0; ib < 2; ++ib) {
+                    const int row = (ip + ib) * 16 + lr;
                     double c[4][4];
 #pragma unroll
-                    for (int ib = 0; ib < 4; ++ib)
+                    for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
-                        for (int g = 0; g < 4; ++g) c[ib][g] = tp[tile_off<S>(ib * 16 + lr, c0 + 4 * g)];
+                        for (int g = 0; g < 4; ++g) c[jb][g] = tp[tile_off<S>(row, jb * 16 + lk + 4 * g)];
 #pragma unroll
-                    for (int ib = 0; ib < 4; ++ib)
+                    for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
-                        for (int g = 0; g < 4; ++g) tp[tile_off<S>(ib * 16 + lr, c0 + 4 * g)] = c[ib][g] - acc[jb][ib][g];
+                        for (int g = 0; g < 4; ++g) tp[tile_off<S>(row, jb * 16 + lk + 4 * g)] = c[jb][g] - acc[jb][ib][g];
                 }
-            }
-        } else {
-            flt4 acc[4][4];
-#pragma unroll
-            for (int jb = 0; jb < 4; ++jb)
-#pragma unroll
-                for (int ib = 0; ib < 4; ++ib) acc[jb][ib] = flt4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-            for (int kk = 0; kk < NB; kk += 4) {
-                const int64_t col = (int64_t)(kk + lk) * LD;
-                float aw[4], av[4], bv[4], bw[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    aw[q] = (float)wJ[col + q * 16]; av[q] = (float)vJ[col + q * 16];
-                    bv[q] = (float)vI[col + q * 16]; bw[q] = (float)wI[col + q * 16];
-                }
+            } else {
+                flt4 acc[4][2];
 #pragma unroll
                 for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
-                    for (int ib = 0; ib < 4; ++ib) {
-                        acc[jb][ib] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw[jb], bv[ib], acc[jb][ib], 0, 0, 0);
-                        acc[jb][ib] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[jb], bw[ib], acc[jb][ib], 0, 0, 0);
+                    for (int ib = 0; ib < 2; ++ib) acc[jb][ib] = flt4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+                for (int kk = 0; kk < NB; kk += 4) {
+                    const int64_t col = (int64_t)(kk + lk) * LD;
+                    const int64_t sc = (int64_t)(kk + lk) * (SLD ? SLD : LD) + lr;
+                    float aw[4], av[4], bv[2], bw[2];
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        bv[q] = (float)vI[col + (ip + q) * 16];
+                        bw[q] = (float)wI[col + (ip + q) * 16];
                     }
-            }
-            // The f32 16x16x4 result holds element (4 lk + g, lr) of the block in
-            // lane (lr + 16 lk), register g: acc[jb][ib][g] = dC(ib*16 + lr, jb*16 + 4 lk + g).
 #pragma unroll
-            for (int jb = 0; jb < 4; ++jb) {
-                float4 c[4];
+                    for (int q = 0; q < 4; ++q) { aw[q] = (float)ws[sc + q * 16]; av[q] = (float)vs[sc + q * 16]; }
 #pragma unroll
-                for (int ib = 0; ib < 4; ++ib)
-                    c[ib] = *reinterpret_cast<const float4 *>(tp + tile_off<S>(ib * 16 + lr, jb * 16 + 4 * lk));
+                    for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
-                for (int ib = 0; ib < 4; ++ib) {
-                    c[ib].x -= acc[jb][ib][0]; c[ib].y -= acc[jb][ib][1];
-                    c[ib].z -= acc[jb][ib][2]; c[ib].w -= acc[jb][ib][3];
-                    *reinterpret_cast<float4 *>(tp + tile_off<S>(ib * 16 + lr, jb * 16 + 4 * lk)) = c[ib];
+                        for (int ib = 0; ib < 2; ++ib)
+                            acc[jb][ib] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw[jb], bv[ib], acc[jb][ib], 0, 0, 0);
+#pragma unroll
+                    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+                        for (int ib = 0; ib < 2; ++ib)
+                            acc[jb][ib] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[jb], bw[ib], acc[jb][ib], 0, 0, 0);
+                }
+                // The f32 16x16x4 result holds element (4 lk + g, lr) of the block in
+                // lane (lr + 16 lk), register g: acc[jb][ib][g] = dC(ib*16 + lr, jb*16 + 4 lk + g).
+#pragma unroll
+                for (int ib = 0; ib < 2; ++ib) {
+                    const int row = (ip + ib) * 16 + lr;
+                    float4 c[4];
+#pragma unroll
+                    for (int jb = 0; jb < 4; ++jb)
+                        c[jb] = *reinterpret_cast<const float4 *>(tp + tile_off<S>(row, jb * 16 + 4 * lk));
+#pragma unroll
+                    for (int jb = 0; jb < 4; ++jb) {
+                        c[jb].x -= acc[jb][ib][0]; c[jb].y -= acc[jb][ib][1];
+                        c[jb].z -= acc[jb][ib][2]; c[jb].w -= acc[jb][ib][3];
+                        *reinterpret_cast<float4 *>(tp + tile_off<S>(row, jb * 16 + 4 * lk)) = c[jb];
+                    }
                 }
             }
         }
     }
 
+    // Trailing update of the tiles J >= J1.  With STAGE, one tile column at a
+    // time with its J-side panel rows in LDS; otherwise every wave takes whole
+    // tiles and reads both sides from the slot (ld = LD).
     __device__ void syr2k(int J1) {
-        int cnt = 0;
-        for (int J = J1; J < T; ++J)
-            for (int I = J; I < T; ++I)
-                if ((cnt++ % NWAVE) == wave) syr2k_tile(I, J);
+        if constexpr (STAGE) {
+            double *vs = stage, *ws = stage + NB * TILE;
+            for (int J = J1; J < T; ++J) {
+                for (int q = tid; q < NB * TILE; q += NT) {
+                    const int kc = q / TILE, r = q % TILE;
+                    vs[q] = V[(int64_t)kc * LD + J * TILE + r];
+                    ws[q] = Wm[(int64_t)kc * LD + J * TILE + r];
+                }
+                __syncthreads();
+                for (int I = J + wave; I < T; I += NWAVE) syr2k_tile<TILE>(I, J, vs, ws);
+                __syncthreads();
+            }
+        } else {
+            int cnt = 0;
+            for (int J = J1; J < T; ++J)
+                for (int I = J; I < T; ++I)
+                    if ((cnt++ % NWAVE) == wave) syr2k_tile<0>(I, J, V + J * TILE, Wm + J * TILE);
+        }
     }
 
     // --------------------------------------------------------- tridiagonalise
@@ -548,7 +602,7 @@ struct Tri {
         const double pad = 2.0 * eps * tnorm * (double)m + 4.0 * pivmin;
         gl -= pad; gu += pad;
         const double atol = eps * tnorm;
-        constexpr int ILP = 4;
+        constexpr int ILP = BILP;
         for (int base = 0; base < m; base += NT * ILP) {
             double lo[ILP], hi[ILP];
             int idx[ILP];
@@ -614,32 +668,37 @@ __host__ __device__ inline int64_t slot_bytes_for(int LDmax) {
     return ((tiles + 255) / 256) * 256 + panel + de;
 }
 
-template <int NB, int NT>
+template <int NB, int NT, bool STAGE>
 __host__ __device__ inline int64_t lds_bytes_for(int LDmax) {
-    return (2 * (int64_t)LDmax + (NT / 64) * (2 * NB + 8)) * 8 + (int64_t)sizeof(Panel<NB>) + 64;
+    return (2 * (int64_t)LDmax + (NT / 64) * (2 * NB + 8) + (STAGE ? 2 * NB * TILE : 0)) * 8 +
+           (int64_t)sizeof(Panel<NB>) + 64;
 }
 
-// NT = 512: one problem per CU (8 waves).  NT = 256: two problems per CU, so
-// that the latency-bound phases of one overlap the HBM stream of the other;
-// at least two waves per SIMD caps the kernel at 256 registers either way.
-template <class S, int NB, int NT>
-__global__ __launch_bounds__(NT, 2) void tridiag_bisect_kernel(TriArgs args) {
+// WPE waves per SIMD: the register budget is 512 / WPE per lane, and the
+// HBM bytes a CU keeps in flight grow with WPE (the SYMV is latency-bound per
+// wave).  NT = 512 with WPE = 2 is one problem per CU; NT = 256 runs
+// 4 * WPE / 4 problems per CU, overlapping the latency-bound phases of one
+// problem with the HBM stream of the others.
+template <class S, int NB, int NT, int CW, bool STAGE, int WPE>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+void tridiag_bisect_kernel(TriArgs args) {
     extern __shared__ double lds[];
     __shared__ int s_item;
-    Tri<S, NB, NT> t;
+    Tri<S, NB, NT, CW, STAGE, (WPE >= 3 ? 2 : 4)> t;
     t.tid = threadIdx.x;
     t.lane = threadIdx.x & 63;
-    t.wave = threadIdx.x >> 6;
+    t.wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: keep in an SGPR
     const int LDmax = args.LDmax;
     t.y = lds;
     t.u = lds + LDmax;
     t.red = lds + 2 * LDmax;
-    t.P = reinterpret_cast<Panel<NB> *>(t.red + (NT / 64) * (2 * NB + 8));
+    t.stage = t.red + (NT / 64) * (2 * NB + 8);
+    t.P = reinterpret_cast<Panel<NB> *>(t.stage + (STAGE ? 2 * NB * TILE : 0));
     char *slot = args.work + (int64_t)blockIdx.x * args.slot_bytes;
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(args.counter, 1);
         __syncthreads();
-        const int64_t it_idx = s_item;
+        const int64_t it_idx = __builtin_amdgcn_readfirstlane(s_item);  // uniform: scalar loads of the item
         __syncthreads();
         if (it_idx >= args.n_items) break;
         const Item it = args.items[it_idx];
