@@ -43,7 +43,7 @@ def symv_bytes(m: int, s: int) -> int:
 
 def kernel_sources_hash() -> str:
     h = hashlib.sha256()
-    for f in ("eeid.hip", "eeid_tridiag.hpp", "eeid_identity.hpp"):
+    for f in ("eeid.hip", "eeid_tridiag.hpp", "eeid_tridiag_c.hpp", "eeid_identity.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2002_04989_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 

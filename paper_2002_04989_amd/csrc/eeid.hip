@@ -17,6 +17,7 @@
 #include "eeid.h"
 #include "eeid_identity.hpp"
 #include "eeid_tridiag.hpp"
+#include "eeid_tridiag_c.hpp"
 
 namespace {
 
@@ -86,7 +87,6 @@ eeid_status_t check_batch(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64_
         if (n[b] > nmax)
             return fail(h, EEID_ERR_UNSUPPORTED, "n[" + std::to_string(b) + "] exceeds the supported maximum");
     }
-    if (t == EEID_C128) return fail(h, EEID_ERR_UNSUPPORTED, "complex Hermitian input is not built yet");
     return EEID_OK;
 }
 
@@ -118,10 +118,12 @@ eeid_status_t upload_desc(eeid_handle_t h, int64_t count, const int64_t *n, cons
     return EEID_OK;
 }
 
-// One compiled configuration of the tridiagonalisation kernel.
-template <class S, int NB, int NT, int CW, bool STAGE, int WPE>
-eeid_status_t launch_tridiag(eeid_handle_t h, const std::vector<eeid::Item> &items,
-                             const std::vector<int64_t> &key, int max_m, const int32_t *flags) {
+// Launch one compiled configuration of the persistent eigenvalue kernel over
+// the problem table: one workgroup per slot, as many slots as fit the device
+// (occupancy x CUs, capped by the problem count and by free memory).
+eeid_status_t launch_persistent(eeid_handle_t h, const void *kern, int nt, int64_t slot, size_t lds,
+                                const std::vector<eeid::Item> &items, const std::vector<int64_t> &key,
+                                int LDmax, const int32_t *flags) {
     using namespace eeid;
     if (items.empty()) return EEID_OK;
     if (key != h->items_key) {
@@ -132,14 +134,10 @@ eeid_status_t launch_tridiag(eeid_handle_t h, const std::vector<eeid::Item> &ite
         h->items_key = key;
         h->n_items = (int64_t)items.size();
     }
-    const int LDmax = ((max_m + TILE - 1) / TILE) * TILE;
-    const int64_t slot = slot_bytes_for<S, NB>(LDmax);
-    const size_t lds = (size_t)lds_bytes_for<NB, NT, STAGE>(LDmax);
-    auto kern = tridiag_bisect_kernel<S, NB, NT, CW, STAGE, WPE>;
-    HIP_TRY(h, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    HIP_TRY(h, hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int per_cu = 0;
-    HIP_TRY(h, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, lds));
-    if (per_cu < 1) return fail(h, EEID_ERR_UNSUPPORTED, "tridiagonalisation kernel cannot be resident");
+    HIP_TRY(h, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, nt, lds));
+    if (per_cu < 1) return fail(h, EEID_ERR_UNSUPPORTED, "eigenvalue kernel cannot be resident");
     int64_t slots = (int64_t)per_cu * h->cu_count;
     slots = std::min<int64_t>(slots, (int64_t)items.size());
     size_t free_b = 0, total_b = 0;
@@ -158,16 +156,39 @@ eeid_status_t launch_tridiag(eeid_handle_t h, const std::vector<eeid::Item> &ite
     a.slot_bytes = slot;
     a.LDmax = LDmax;
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, h->stream, h->counter);
-    hipLaunchKernelGGL(kern, dim3((unsigned)slots), dim3(NT), lds, h->stream, a);
-    HIP_TRY(h, hipGetLastError());
+    void *argv[] = {&a};
+    HIP_TRY(h, hipLaunchKernel(kern, dim3((unsigned)slots), dim3((unsigned)nt), argv, lds, h->stream));
     return EEID_OK;
+}
+
+template <class S, int NB, int NT, int CW, bool STAGE, int WPE>
+eeid_status_t launch_tridiag(eeid_handle_t h, const std::vector<eeid::Item> &items,
+                             const std::vector<int64_t> &key, int max_m, const int32_t *flags) {
+    using namespace eeid;
+    const int LDmax = ((max_m + TILE - 1) / TILE) * TILE;
+    return launch_persistent(h, (const void *)tridiag_bisect_kernel<S, NB, NT, CW, STAGE, WPE>, NT,
+                             slot_bytes_for<S, NB>(LDmax), (size_t)lds_bytes_for<NB, NT, STAGE>(LDmax), items, key,
+                             LDmax, flags);
+}
+
+template <class R, int NB, int NT, int CW>
+eeid_status_t launch_tridiag_c(eeid_handle_t h, const std::vector<eeid::Item> &items,
+                               const std::vector<int64_t> &key, int max_m, const int32_t *flags) {
+    using namespace eeid;
+    const int LDmax = ((max_m + TILE - 1) / TILE) * TILE;
+    return launch_persistent(h, (const void *)tridiag_bisect_kernel_c<R, NB, NT, CW>, NT, slot_bytes_c<R, NB>(LDmax),
+                             (size_t)lds_bytes_c<NB, NT>(LDmax), items, key, LDmax, flags);
 }
 
 // Kernel configurations: (panel width NB, threads NT, SYMV unit width CW,
 // LDS staging of the trailing update, waves per SIMD).
-eeid_status_t dispatch_variant(eeid_handle_t h, eeid_prec_t p, const std::vector<eeid::Item> &items,
-                               const std::vector<int64_t> &key, int nmax, const int32_t *flags) {
+eeid_status_t dispatch_variant(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p,
+                               const std::vector<eeid::Item> &items, const std::vector<int64_t> &key, int nmax,
+                               const int32_t *flags) {
     const bool d = (p == EEID_PREC_FP64);
+    if (t == EEID_C128)  // complex: panel 16, 16-column SYMV units, no LDS staging
+        return d ? launch_tridiag_c<double, 16, 512, 16>(h, items, key, nmax, flags)
+                 : launch_tridiag_c<float, 16, 512, 16>(h, items, key, nmax, flags);
     switch (h->variant) {
         case 1:
             return d ? launch_tridiag<double, 32, 256, 32, true, 2>(h, items, key, nmax, flags)
@@ -180,7 +201,7 @@ eeid_status_t dispatch_variant(eeid_handle_t h, eeid_prec_t p, const std::vector
 
 // kind 0: eigenvalues of the matrices only; kind 1: matrices and all minors;
 // kind 2: one matrix and a subset of minors.
-eeid_status_t run_eigs(eeid_handle_t h, eeid_prec_t p, int64_t count, const int64_t *n,
+eeid_status_t run_eigs(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64_t count, const int64_t *n,
                        const int64_t *a_offset, const void *A, double *lambda, double *mu,
                        int32_t *flags, int kind, int64_t nsel, const int64_t *js) {
     using eeid::Item;
@@ -190,6 +211,7 @@ eeid_status_t run_eigs(eeid_handle_t h, eeid_prec_t p, int64_t count, const int6
     const eeid::BatchDesc *desc = reinterpret_cast<const eeid::BatchDesc *>(h->desc.p);
     std::vector<int64_t> key;
     key.push_back(kind);
+    key.push_back((int64_t)t);
     key.push_back((int64_t)p);
     key.push_back((int64_t)(intptr_t)A);
     key.push_back((int64_t)(intptr_t)lambda);
@@ -201,16 +223,18 @@ eeid_status_t run_eigs(eeid_handle_t h, eeid_prec_t p, int64_t count, const int6
     std::vector<Item> items;
     int64_t nmax = 0, lam = 0, muo = 0;
     const double *Ad = reinterpret_cast<const double *>(A);
+    const int64_t esz = (t == EEID_C128) ? 2 : 1;  // doubles per element
     for (int64_t b = 0; b < count; ++b) {
         const int nb = (int)n[b];
+        const double *src = Ad + esz * a_offset[b];
         nmax = std::max<int64_t>(nmax, nb);
-        if (lambda) items.push_back(Item{Ad + a_offset[b], lambda + lam, nb, -1, nb, (int32_t)b});
+        if (lambda) items.push_back(Item{src, lambda + lam, nb, -1, nb, (int32_t)b});
         if (kind == 1 && nb >= 2)
             for (int j = 0; j < nb; ++j)
-                items.push_back(Item{Ad + a_offset[b], mu + muo + (int64_t)j * (nb - 1), nb, j, nb - 1, (int32_t)b});
+                items.push_back(Item{src, mu + muo + (int64_t)j * (nb - 1), nb, j, nb - 1, (int32_t)b});
         if (kind == 2 && nb >= 2)
             for (int64_t q = 0; q < nsel; ++q)
-                items.push_back(Item{Ad + a_offset[b], mu + q * (nb - 1), nb, (int)js[q], nb - 1, (int32_t)b});
+                items.push_back(Item{src, mu + q * (nb - 1), nb, (int)js[q], nb - 1, (int32_t)b});
         lam += nb;
         muo += (int64_t)nb * (nb - 1);
     }
@@ -221,9 +245,9 @@ eeid_status_t run_eigs(eeid_handle_t h, eeid_prec_t p, int64_t count, const int6
     hipLaunchKernelGGL(eeid::prep_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, h->stream,
                        flags, count, (int *)nullptr);
     hipLaunchKernelGGL(eeid::nonfinite_kernel, dim3((unsigned)nn_blocks, (unsigned)count), dim3(256), 0,
-                       h->stream, desc, Ad, 0, flags);
+                       h->stream, desc, Ad, t == EEID_C128 ? 1 : 0, flags);
     HIP_TRY(h, hipGetLastError());
-    return dispatch_variant(h, p, items, key, (int)nmax, flags);
+    return dispatch_variant(h, t, p, items, key, (int)nmax, flags);
 }
 
 }  // namespace
@@ -292,7 +316,7 @@ eeid_status_t eeid_eigvalsh_batched(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t
     eeid_status_t s = check_batch(h, t, p, count, n, a_offset, A);
     if (s != EEID_OK) return s;
     if (!lambda || !flags) return fail(h, EEID_ERR_INVALID_ARG, "null output pointer");
-    return run_eigs(h, p, count, n, a_offset, A, lambda, nullptr, flags, 0, 0, nullptr);
+    return run_eigs(h, t, p, count, n, a_offset, A, lambda, nullptr, flags, 0, 0, nullptr);
 }
 
 eeid_status_t eeid_minor_eigvals(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64_t count,
@@ -304,7 +328,7 @@ eeid_status_t eeid_minor_eigvals(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p,
     bool need_mu = false;
     for (int64_t b = 0; b < count; ++b) need_mu = need_mu || n[b] >= 2;
     if (need_mu && !mu) return fail(h, EEID_ERR_INVALID_ARG, "mu is null");
-    return run_eigs(h, p, count, n, a_offset, A, lambda, mu, flags, 1, 0, nullptr);
+    return run_eigs(h, t, p, count, n, a_offset, A, lambda, mu, flags, 1, 0, nullptr);
 }
 
 eeid_status_t eeid_minor_eigvals_subset(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64_t n,
@@ -318,7 +342,7 @@ eeid_status_t eeid_minor_eigvals_subset(eeid_handle_t h, eeid_dtype_t t, eeid_pr
     if (n >= 2 && !mu_sel) return fail(h, EEID_ERR_INVALID_ARG, "mu_sel is null");
     for (int64_t q = 0; q < nsel; ++q)
         if (js[q] < 0 || js[q] >= n) return fail(h, EEID_ERR_INVALID_ARG, "js entry out of range");
-    return run_eigs(h, p, 1, &n, &zero, A, lambda, mu_sel, flag, 2, nsel, js);
+    return run_eigs(h, t, p, 1, &n, &zero, A, lambda, mu_sel, flag, 2, nsel, js);
 }
 
 eeid_status_t eeid_components(eeid_handle_t h, int64_t count, const int64_t *n, const double *lambda,

@@ -110,6 +110,88 @@ struct Panel {
     double tmp[2 * NB + 8];
 };
 
+// All eigenvalues of the symmetric tridiagonal (d, e) ascending, by Sturm
+// counts: count(x) = #{i : q_i < 0}, q_0 = d_0 - x, q_i = d_i - x - e_{i-1}^2 / q_{i-1},
+// tiny pivots replaced by -pivmin.  Bisection from a widened Gershgorin
+// interval stops at ulp level (relative 2 eps, absolute eps ||T||), at most
+// 80 halvings.  One lane per eigenvalue, ILP eigenvalues per lane in
+// lockstep; de (LDS, >= 2m doubles) receives (d_i, e_{i-1}^2) pairs, red
+// (LDS) the workgroup reductions.
+template <int NT, int ILP>
+__device__ void bisect_tridiagonal(const double *dg, const double *eg, int m, double *out, double *de,
+                                   double *red, int tid, int lane, int wave) {
+    constexpr int NWAVE = NT / 64;
+    double gl = 1e308, gu = -1e308, emax2 = 0.0;
+    for (int i = tid; i < m; i += NT) {
+        const double d = dg[i];
+        const double el = (i > 0) ? fabs(eg[i - 1]) : 0.0;
+        const double er = (i < m - 1) ? fabs(eg[i]) : 0.0;
+        de[2 * i] = d;
+        de[2 * i + 1] = el * el;
+        gl = fmin(gl, d - el - er);
+        gu = fmax(gu, d + el + er);
+        emax2 = fmax(emax2, el * el);
+    }
+    gl = wave_min(gl); gu = wave_max(gu); emax2 = wave_max(emax2);
+    if (lane == 0) {
+        red[wave * 4 + 0] = gl; red[wave * 4 + 1] = gu; red[wave * 4 + 2] = emax2;
+    }
+    __syncthreads();
+    gl = 1e308; gu = -1e308; emax2 = 0.0;
+    for (int w = 0; w < NWAVE; ++w) {
+        gl = fmin(gl, red[w * 4]); gu = fmax(gu, red[w * 4 + 1]); emax2 = fmax(emax2, red[w * 4 + 2]);
+    }
+    const double eps = 2.220446049250313e-16;
+    const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
+    const double tnorm = fmax(fabs(gl), fabs(gu));
+    const double pad = 2.0 * eps * tnorm * (double)m + 4.0 * pivmin;
+    gl -= pad; gu += pad;
+    const double atol = eps * tnorm;
+    for (int base = 0; base < m; base += NT * ILP) {
+        double lo[ILP], hi[ILP];
+        int idx[ILP];
+        bool done[ILP];
+#pragma unroll
+        for (int t = 0; t < ILP; ++t) {
+            idx[t] = base + t * NT + tid;
+            lo[t] = gl; hi[t] = gu;
+            done[t] = idx[t] >= m;
+        }
+        for (int it = 0; it < 80; ++it) {
+            bool all = true;
+#pragma unroll
+            for (int t = 0; t < ILP; ++t) all = all && done[t];
+            if (all) break;
+            double x[ILP], q[ILP];
+            int cnt[ILP];
+#pragma unroll
+            for (int t = 0; t < ILP; ++t) { x[t] = 0.5 * (lo[t] + hi[t]); q[t] = 1.0; cnt[t] = 0; }
+            for (int i = 0; i < m; ++i) {
+                const double d = de[2 * i], e2 = de[2 * i + 1];
+#pragma unroll
+                for (int t = 0; t < ILP; ++t) {
+                    double v = (d - x[t]) - e2 / q[t];
+                    v = (fabs(v) < pivmin) ? -pivmin : v;
+                    cnt[t] += (v < 0.0) ? 1 : 0;
+                    q[t] = v;
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < ILP; ++t) {
+                if (done[t]) continue;
+                if (cnt[t] > idx[t]) hi[t] = x[t]; else lo[t] = x[t];
+                const double w = hi[t] - lo[t];
+                const double mid = 0.5 * (lo[t] + hi[t]);
+                if (w <= fmax(2.0 * eps * fmax(fabs(lo[t]), fabs(hi[t])), atol) || mid <= lo[t] || mid >= hi[t])
+                    done[t] = true;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < ILP; ++t)
+            if (idx[t] < m) out[idx[t]] = 0.5 * (lo[t] + hi[t]);
+    }
+}
+
 // S: storage type of the trailing matrix; NB: panel width; NT: threads per
 // workgroup; CW: columns per SYMV work unit (32 or 16); STAGE: stage the
 // trailing update's J-side panel rows in LDS; BILP: eigenvalues bisected
@@ -571,82 +653,7 @@ struct Tri {
     }
 
     // ------------------------------------------------------------- bisection
-    // All eigenvalues of the symmetric tridiagonal (dg, eg) ascending, by
-    // Sturm counts: count(x) = #{i : q_i < 0}, q_0 = d_0 - x,
-    // q_i = d_i - x - e_{i-1}^2 / q_{i-1}, tiny pivots replaced by -pivmin.
-    __device__ void bisect(double *out) {
-        double *de = y;  // reuse: de[2i] = d_i, de[2i+1] = e_{i-1}^2
-        double gl = 1e308, gu = -1e308, emax2 = 0.0;
-        for (int i = tid; i < m; i += NT) {
-            const double d = dg[i];
-            const double el = (i > 0) ? fabs(eg[i - 1]) : 0.0;
-            const double er = (i < m - 1) ? fabs(eg[i]) : 0.0;
-            de[2 * i] = d;
-            de[2 * i + 1] = el * el;
-            gl = fmin(gl, d - el - er);
-            gu = fmax(gu, d + el + er);
-            emax2 = fmax(emax2, el * el);
-        }
-        gl = wave_min(gl); gu = wave_max(gu); emax2 = wave_max(emax2);
-        if (lane == 0) {
-            red[wave * 4 + 0] = gl; red[wave * 4 + 1] = gu; red[wave * 4 + 2] = emax2;
-        }
-        __syncthreads();
-        gl = 1e308; gu = -1e308; emax2 = 0.0;
-        for (int w = 0; w < NWAVE; ++w) {
-            gl = fmin(gl, red[w * 4]); gu = fmax(gu, red[w * 4 + 1]); emax2 = fmax(emax2, red[w * 4 + 2]);
-        }
-        const double eps = 2.220446049250313e-16;
-        const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
-        const double tnorm = fmax(fabs(gl), fabs(gu));
-        const double pad = 2.0 * eps * tnorm * (double)m + 4.0 * pivmin;
-        gl -= pad; gu += pad;
-        const double atol = eps * tnorm;
-        constexpr int ILP = BILP;
-        for (int base = 0; base < m; base += NT * ILP) {
-            double lo[ILP], hi[ILP];
-            int idx[ILP];
-            bool done[ILP];
-#pragma unroll
-            for (int t = 0; t < ILP; ++t) {
-                idx[t] = base + t * NT + tid;
-                lo[t] = gl; hi[t] = gu;
-                done[t] = idx[t] >= m;
-            }
-            for (int it = 0; it < 80; ++it) {
-                bool all = true;
-#pragma unroll
-                for (int t = 0; t < ILP; ++t) all = all && done[t];
-                if (all) break;
-                double x[ILP], q[ILP];
-                int cnt[ILP];
-#pragma unroll
-                for (int t = 0; t < ILP; ++t) { x[t] = 0.5 * (lo[t] + hi[t]); q[t] = 1.0; cnt[t] = 0; }
-                for (int i = 0; i < m; ++i) {
-                    const double d = de[2 * i], e2 = de[2 * i + 1];
-#pragma unroll
-                    for (int t = 0; t < ILP; ++t) {
-                        double v = (d - x[t]) - e2 / q[t];
-                        v = (fabs(v) < pivmin) ? -pivmin : v;
-                        cnt[t] += (v < 0.0) ? 1 : 0;
-                        q[t] = v;
-                    }
-                }
-#pragma unroll
-                for (int t = 0; t < ILP; ++t) {
-                    if (done[t]) continue;
-                    if (cnt[t] > idx[t]) hi[t] = x[t]; else lo[t] = x[t];
-                    const double w = hi[t] - lo[t];
-                    const double mid = 0.5 * (lo[t] + hi[t]);
-                    if (w <= fmax(2.0 * eps * fmax(fabs(lo[t]), fabs(hi[t])), atol) || mid <= lo[t] || mid >= hi[t])
-                        done[t] = true;
-                }
-            }
-#pragma unroll
-            for (int t = 0; t < ILP; ++t)
-                if (idx[t] < m) out[idx[t]] = 0.5 * (lo[t] + hi[t]);
-        }
-    }
+    __device__ void bisect(double *out) { bisect_tridiagonal<NT, BILP>(dg, eg, m, out, y, red, tid, lane, wave); }
 };
 
 struct TriArgs {

@@ -168,3 +168,65 @@ def test_fp32_trailing_form_error_is_bounded():
     assert dl < 8 * np.sqrt(n) * 2.0 ** -24 and dm < 8 * np.sqrt(n) * 2.0 ** -24
     assert dw < 1e-2
     assert flag == 0
+
+
+# ------------------------------------------------------------ complex Hermitian
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 33, 64, 65, 100, 130])
+def test_gue_sizes(n):
+    announce(f"gue n={n}")
+    A = inputs.gue(n, 300 + n)
+    check(A, run_all([A])[0])
+
+
+def test_complex_2x2_closed_form():
+    announce("complex 2x2 closed form")
+    import math
+    for seed in range(5):
+        r = np.random.default_rng(seed)
+        a, c = r.standard_normal(2)
+        b = complex(r.standard_normal(), r.standard_normal())
+        A = np.array([[a, np.conj(b)], [b, c]], dtype=np.complex128)
+        lam, mu, W, flag = run_all([A])[0]
+        mid, rad = 0.5 * (a + c), math.sqrt((0.5 * (a - c)) ** 2 + abs(b) ** 2)
+        lx = np.array([mid - rad, mid + rad])
+        np.testing.assert_allclose(lam, lx, atol=1e-14)
+        Wx = np.array([[(lx[i] - c) / (lx[i] - lx[1 - i]), (lx[i] - a) / (lx[i] - lx[1 - i])] for i in range(2)])
+        np.testing.assert_allclose(W, Wx, atol=1e-13)
+
+
+def test_complex_uneven_batch_and_conventions():
+    sizes = [5, 64, 1, 90, 33]
+    announce(f"complex batch {sizes}")
+    mats = [inputs.gue(n, [11, n]) for n in sizes]
+    B = mats[1].copy()
+    B[np.diag_indices(64)] += 5j                 # imaginary diagonal ignored
+    B[np.triu_indices(64, 1)] = 7.0 + 3.0j       # upper triangle ignored
+    res = run_all(mats + [B])
+    for A, got in zip(mats, res[:-1]):
+        check(A, got)
+    np.testing.assert_allclose(res[-1][2], res[1][2], atol=1e-13, rtol=0)
+
+
+def test_complex_diagonal_real():
+    announce("complex diagonal")
+    d = np.array([2.0, -1.0, 0.5, 9.0])
+    lam, mu, W, flag = run_all([np.diag(d).astype(np.complex128)])[0]
+    P = np.zeros((4, 4))
+    P[np.arange(4), np.argsort(d)] = 1.0
+    np.testing.assert_allclose(W, P, atol=1e-13)
+
+
+def test_c64_trailing_form_error_is_bounded():
+    n = 120
+    announce(f"c64 trailing form n={n}")
+    A = inputs.gue(n, 91)
+    lam_o, mu_o, W_o, _ = oracle.components_identity(A)
+    lam, mu, W, flag = run_all([A], prec="fp32")[0]
+    s = norm2(A)
+    dl = np.max(np.abs(lam - lam_o)) / s
+    dm = np.max(np.abs(mu - mu_o)) / s
+    dw = np.max(np.abs(W - W_o))
+    print(f"c64 form n={n}: max|dlam|/||A||={dl:.2e} max|dmu|/||A||={dm:.2e} max|dW|={dw:.2e}")
+    assert dl < 8 * np.sqrt(n) * 2.0 ** -24 and dm < 8 * np.sqrt(n) * 2.0 ** -24
+    assert dw < 1e-2
+    assert flag == 0
