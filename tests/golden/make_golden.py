@@ -17,6 +17,7 @@ import os
 import platform
 import sys
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -55,7 +56,14 @@ def make(name: str) -> None:
     A, js, method = WORKLOADS[name]()
     threads = oracle.default_threads()
     t0 = time.time()
-    lam, mu, W, flags = oracle.components_identity(A, js=js, method=method, threads=threads)
+    # lambda(A) and the sampled minors run concurrently (one eigenvalue problem per thread)
+    Ah = oracle.hermitian_from_lower(A)
+    with ThreadPoolExecutor(min(threads, len(js) + 1)) as ex:
+        f_lam = ex.submit(oracle.eigvalsh, Ah, method)
+        f_mu = [ex.submit(oracle.eigvalsh, oracle.minor(Ah, j), method) for j in js]
+        lam = f_lam.result()
+        mu = np.array([f.result() for f in f_mu])
+    W, flags = oracle.identity_from_spectra(lam, mu)
     dt = time.time() - t0
     np.savez(os.path.join(HERE, f"{name}.npz"), js=np.array(js, dtype=np.int64), lam=lam, mu=mu, W=W,
              flags=np.array([flags], dtype=np.int32))
