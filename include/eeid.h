@@ -144,12 +144,40 @@ eeid_status_t eeid_components(eeid_handle_t h, int64_t count, const int64_t *n,
                               const double *lambda, const double *mu, double *V2,
                               int32_t *flags);
 
+/* Columns of Eq. (2) for a subset of minors of ONE matrix of order n: the
+ * squared components j_s of every eigenvector, from lambda(A) and the spectra
+ * of the chosen minors (as eeid_minor_eigvals_subset writes them).  With one
+ * minor this is the single-component query of Table 1 for every i at once.
+ *   lambda  device [n];  mu_sel device [nsel * (n - 1)]
+ *   V2_sel  device [n * nsel] output, V2_sel[i * nsel + s] = |v_i(j_s)|^2
+ *   flag    device [1], EEID_FLAG_DEGENERATE is OR-ed in */
+eeid_status_t eeid_components_subset(eeid_handle_t h, int64_t n, const double *lambda, int64_t nsel,
+                                     const double *mu_sel, double *V2_sel, int32_t *flag);
+
 /* eeid_minor_eigvals followed by eeid_components: every |v_ij|^2 of every
- * matrix of the batch from device-resident A to device-resident V2. */
+ * matrix of the batch from device-resident A to device-resident V2.  In graph
+ * mode (eeid_set_graph_mode) the launches are recorded once per argument set
+ * into a hipGraph and replayed on a private stream ordered after, and before,
+ * the handle's stream. */
 eeid_status_t eeid_all_components(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p,
                                   int64_t count, const int64_t *n, const int64_t *a_offset,
                                   const void *A, double *lambda, double *mu, double *V2,
                                   int32_t *flags);
+
+/* Enable (1) or disable (0) graph mode for eeid_all_components. */
+eeid_status_t eeid_set_graph_mode(eeid_handle_t h, int enable);
+
+/* Time every compiled configuration of the eigenvalue kernel on this batch
+ * (one eeid_minor_eigvals each, outputs written to lambda/mu/flags) and use
+ * the fastest for batches of the same dtype, precision, largest order and
+ * problem count from now on.  If the environment variable EEID_TUNE_TABLE
+ * names a file, the choice is appended to it ("dtype prec n_max problems
+ * variant  # name ms") and eeid_create loads it.  Synchronises the stream.
+ *   best_variant, best_ms  host outputs (may be NULL) */
+eeid_status_t eeid_autotune(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p,
+                            int64_t count, const int64_t *n, const int64_t *a_offset,
+                            const void *A, double *lambda, double *mu, int32_t *flags,
+                            int *best_variant, double *best_ms);
 
 #ifdef __cplusplus
 }

@@ -1,16 +1,24 @@
 // libeeid host runtime: the C ABI declared in include/eeid.h.
 //
-// Validation, workspace, the (matrix, minor) problem table and kernel
-// launches.  All arithmetic of the method runs in the kernels of
-// eeid_tridiag.hpp (eigenvalues of A and of its minors) and eeid_identity.hpp
-// (Eq. (2) of the paper); the host only schedules.
+// Validation, workspace, the (matrix, minor) problem table, kernel selection
+// (autotuned), optional hipGraph capture and kernel launches.  All arithmetic
+// of the method runs in the kernels of eeid_tridiag.hpp / eeid_tridiag_c.hpp
+// (eigenvalues of A and of its minors) and eeid_identity.hpp (Eq. (2) of the
+// paper); the host only schedules.
+//
+// Every entry point is split into a prepare step (argument checks, uploads of
+// descriptor tables, workspace growth -- host-synchronous, never captured)
+// and an enqueue step (kernel launches only), so that the enqueue steps can
+// be recorded into a hipGraph and replayed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -21,11 +29,17 @@
 
 namespace {
 
-
 struct Buf {
     void *p = nullptr;
     size_t bytes = 0;
 };
+
+typedef std::function<hipError_t(hipStream_t)> Enqueue;
+
+// Compiled configurations of the real eigenvalue kernel (the complex kernel
+// has one): panel width NB and threads per workgroup.
+constexpr int N_REAL_VARIANTS = 3;
+const char *const VARIANT_NAME[N_REAL_VARIANTS] = {"nb32_nt512", "nb32_nt256x2", "nb16_nt512"};
 
 }  // namespace
 
@@ -34,11 +48,22 @@ struct eeid_handle_s {
     hipStream_t stream = nullptr;
     int cu_count = 0;
     std::string err;
-    Buf work, items, desc, dpair, flags1;
+    Buf work, items, desc, desc_sub, dpair, dpair_sub;
     int *counter = nullptr;
-    std::vector<int64_t> items_key, desc_key;
+    std::vector<int64_t> items_key, desc_key, desc_sub_key;
     int64_t n_items = 0;
-    int variant = 0;  // kernel configuration (dispatch_variant)
+    int variant = 0;            // real-kernel configuration when the tune table has no entry
+    int forced_variant = -1;    // >= 0: use this configuration (autotuning, EEID_VARIANT)
+    uint64_t generation = 0;    // bumped whenever a buffer the kernels read is reallocated or rewritten
+    // graph mode
+    bool graph_mode = false;
+    hipStream_t gstream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<int64_t> gkey;
+    // tune table: {dtype, prec, n_max, problems, variant}
+    std::vector<std::array<int64_t, 5>> tune;
+    std::string tune_path;
 };
 
 namespace {
@@ -55,20 +80,45 @@ eeid_status_t fail(eeid_handle_t h, eeid_status_t s, const std::string &msg) {
             return fail((h), EEID_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-// Grow `b` to at least `bytes`; the stream is drained first so no queued
-// kernel still reads the old allocation.
+// Drain every stream the handle launches on.
+eeid_status_t drain(eeid_handle_t h) {
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    if (h->gstream) HIP_TRY(h, hipStreamSynchronize(h->gstream));
+    return EEID_OK;
+}
+
+// Grow `b` to at least `bytes`; queued work is drained first so no kernel
+// still reads the old allocation, and captured graphs are invalidated.
 eeid_status_t ensure(eeid_handle_t h, Buf &b, size_t bytes) {
     if (b.bytes >= bytes) return EEID_OK;
-    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    eeid_status_t s = drain(h);
+    if (s != EEID_OK) return s;
     if (b.p) HIP_TRY(h, hipFree(b.p));
     b.p = nullptr;
     b.bytes = 0;
+    ++h->generation;
     if (hipMalloc(&b.p, bytes) != hipSuccess) {
         (void)hipGetLastError();
         b.p = nullptr;
         return fail(h, EEID_ERR_ALLOC, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
     }
     b.bytes = bytes;
+    return EEID_OK;
+}
+
+// Upload a host table to `b` when `key` differs from the cached one.
+template <class T>
+eeid_status_t upload_table(eeid_handle_t h, Buf &b, std::vector<int64_t> &cached, std::vector<int64_t> &key,
+                           const std::vector<T> &rows) {
+    if (key == cached) return EEID_OK;
+    eeid_status_t s = ensure(h, b, sizeof(T) * std::max<size_t>(rows.size(), 1));
+    if (s != EEID_OK) return s;
+    s = drain(h);
+    if (s != EEID_OK) return s;
+    if (!rows.empty())
+        HIP_TRY(h, hipMemcpy(b.p, rows.data(), sizeof(T) * rows.size(), hipMemcpyHostToDevice));
+    cached.swap(key);
+    ++h->generation;
     return EEID_OK;
 }
 
@@ -90,135 +140,78 @@ eeid_status_t check_batch(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64_
     return EEID_OK;
 }
 
-// Per-matrix descriptors (offsets of every output); cached on the batch shape.
-eeid_status_t upload_desc(eeid_handle_t h, int64_t count, const int64_t *n, const int64_t *a_offset) {
+// Per-matrix descriptors (offsets of every output).  ncol < 0: all n columns.
+eeid_status_t upload_desc(eeid_handle_t h, Buf &buf, std::vector<int64_t> &cached, int64_t count,
+                          const int64_t *n, const int64_t *a_offset, int64_t ncol) {
     std::vector<int64_t> key;
-    key.reserve(2 * count + 1);
+    key.reserve(2 * count + 2);
     key.push_back(count);
+    key.push_back(ncol);
     for (int64_t b = 0; b < count; ++b) { key.push_back(n[b]); key.push_back(a_offset ? a_offset[b] : 0); }
-    if (key == h->desc_key) return EEID_OK;
     std::vector<eeid::BatchDesc> d(count);
     int64_t lam = 0, mu = 0, v2 = 0;
     for (int64_t b = 0; b < count; ++b) {
+        const int64_t nc = (ncol < 0) ? n[b] : ncol;
         d[b].a_off = a_offset ? a_offset[b] : 0;
         d[b].lam_off = lam;
         d[b].mu_off = mu;
         d[b].v2_off = v2;
         d[b].n = (int32_t)n[b];
-        d[b].pad = 0;
+        d[b].ncol = (int32_t)nc;
         lam += n[b];
-        mu += n[b] * (n[b] - 1);
-        v2 += n[b] * n[b];
+        mu += nc * (n[b] - 1);
+        v2 += n[b] * nc;
     }
-    eeid_status_t s = ensure(h, h->desc, sizeof(eeid::BatchDesc) * count);
-    if (s != EEID_OK) return s;
-    HIP_TRY(h, hipStreamSynchronize(h->stream));
-    HIP_TRY(h, hipMemcpy(h->desc.p, d.data(), sizeof(eeid::BatchDesc) * count, hipMemcpyHostToDevice));
-    h->desc_key.swap(key);
-    return EEID_OK;
+    return upload_table(h, buf, cached, key, d);
 }
 
-// Launch one compiled configuration of the persistent eigenvalue kernel over
-// the problem table: one workgroup per slot, as many slots as fit the device
-// (occupancy x CUs, capped by the problem count and by free memory).
-eeid_status_t launch_persistent(eeid_handle_t h, const void *kern, int nt, int64_t slot, size_t lds,
-                                const std::vector<eeid::Item> &items, const std::vector<int64_t> &key,
-                                int LDmax, const int32_t *flags) {
+struct KernelChoice {
+    const void *kern;
+    int nt;
+    int64_t slot;
+    size_t lds;
+};
+
+template <class S, int NB, int NT>
+KernelChoice real_kernel(int LDmax) {
     using namespace eeid;
-    if (items.empty()) return EEID_OK;
-    if (key != h->items_key) {
-        eeid_status_t s = ensure(h, h->items, sizeof(Item) * items.size());
-        if (s != EEID_OK) return s;
-        HIP_TRY(h, hipStreamSynchronize(h->stream));
-        HIP_TRY(h, hipMemcpy(h->items.p, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice));
-        h->items_key = key;
-        h->n_items = (int64_t)items.size();
-    }
-    HIP_TRY(h, hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    int per_cu = 0;
-    HIP_TRY(h, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, nt, lds));
-    if (per_cu < 1) return fail(h, EEID_ERR_UNSUPPORTED, "eigenvalue kernel cannot be resident");
-    int64_t slots = (int64_t)per_cu * h->cu_count;
-    slots = std::min<int64_t>(slots, (int64_t)items.size());
-    size_t free_b = 0, total_b = 0;
-    HIP_TRY(h, hipMemGetInfo(&free_b, &total_b));
-    const size_t budget = (size_t)((double)(free_b + h->work.bytes) * 0.85);
-    slots = std::min<int64_t>(slots, (int64_t)(budget / (size_t)slot));
-    if (slots < 1) return fail(h, EEID_ERR_ALLOC, "not enough device memory for one problem slot");
-    eeid_status_t s = ensure(h, h->work, (size_t)(slots * slot));
-    if (s != EEID_OK) return s;
-    TriArgs a;
-    a.items = reinterpret_cast<const Item *>(h->items.p);
-    a.n_items = h->n_items;
-    a.counter = h->counter;
-    a.flags = flags;
-    a.work = reinterpret_cast<char *>(h->work.p);
-    a.slot_bytes = slot;
-    a.LDmax = LDmax;
-    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, h->stream, h->counter);
-    void *argv[] = {&a};
-    HIP_TRY(h, hipLaunchKernel(kern, dim3((unsigned)slots), dim3((unsigned)nt), argv, lds, h->stream));
-    return EEID_OK;
+    return {(const void *)tridiag_bisect_kernel<S, NB, NT, 32, true, 2>, NT, slot_bytes_for<S, NB>(LDmax),
+            (size_t)lds_bytes_for<NB, NT, true>(LDmax)};
 }
 
-template <class S, int NB, int NT, int CW, bool STAGE, int WPE>
-eeid_status_t launch_tridiag(eeid_handle_t h, const std::vector<eeid::Item> &items,
-                             const std::vector<int64_t> &key, int max_m, const int32_t *flags) {
+template <class R, int NB, int NT>
+KernelChoice complex_kernel(int LDmax) {
     using namespace eeid;
-    const int LDmax = ((max_m + TILE - 1) / TILE) * TILE;
-    return launch_persistent(h, (const void *)tridiag_bisect_kernel<S, NB, NT, CW, STAGE, WPE>, NT,
-                             slot_bytes_for<S, NB>(LDmax), (size_t)lds_bytes_for<NB, NT, STAGE>(LDmax), items, key,
-                             LDmax, flags);
+    return {(const void *)tridiag_bisect_kernel_c<R, NB, NT, 16>, NT, slot_bytes_c<R, NB>(LDmax),
+            (size_t)lds_bytes_c<NB, NT>(LDmax)};
 }
 
-template <class R, int NB, int NT, int CW>
-eeid_status_t launch_tridiag_c(eeid_handle_t h, const std::vector<eeid::Item> &items,
-                               const std::vector<int64_t> &key, int max_m, const int32_t *flags) {
-    using namespace eeid;
-    const int LDmax = ((max_m + TILE - 1) / TILE) * TILE;
-    return launch_persistent(h, (const void *)tridiag_bisect_kernel_c<R, NB, NT, CW>, NT, slot_bytes_c<R, NB>(LDmax),
-                             (size_t)lds_bytes_c<NB, NT>(LDmax), items, key, LDmax, flags);
-}
-
-// Kernel configurations: (panel width NB, threads NT, SYMV unit width CW,
-// LDS staging of the trailing update, waves per SIMD).
-eeid_status_t dispatch_variant(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p,
-                               const std::vector<eeid::Item> &items, const std::vector<int64_t> &key, int nmax,
-                               const int32_t *flags) {
+KernelChoice choose_kernel(eeid_dtype_t t, eeid_prec_t p, int variant, int LDmax) {
     const bool d = (p == EEID_PREC_FP64);
-    if (t == EEID_C128)  // complex: panel 16, 16-column SYMV units, no LDS staging
-        return d ? launch_tridiag_c<double, 16, 512, 16>(h, items, key, nmax, flags)
-                 : launch_tridiag_c<float, 16, 512, 16>(h, items, key, nmax, flags);
-    switch (h->variant) {
-        case 1:
-            return d ? launch_tridiag<double, 32, 256, 32, true, 2>(h, items, key, nmax, flags)
-                     : launch_tridiag<float, 32, 256, 32, true, 2>(h, items, key, nmax, flags);
-        default:
-            return d ? launch_tridiag<double, 32, 512, 32, true, 2>(h, items, key, nmax, flags)
-                     : launch_tridiag<float, 32, 512, 32, true, 2>(h, items, key, nmax, flags);
+    if (t == EEID_C128) return d ? complex_kernel<double, 16, 512>(LDmax) : complex_kernel<float, 16, 512>(LDmax);
+    switch (variant) {
+        case 1: return d ? real_kernel<double, 32, 256>(LDmax) : real_kernel<float, 32, 256>(LDmax);
+        case 2: return d ? real_kernel<double, 16, 512>(LDmax) : real_kernel<float, 16, 512>(LDmax);
+        default: return d ? real_kernel<double, 32, 512>(LDmax) : real_kernel<float, 32, 512>(LDmax);
     }
+}
+
+int pick_variant(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64_t nmax, int64_t problems) {
+    if (h->forced_variant >= 0) return h->forced_variant;
+    for (const auto &e : h->tune)
+        if (e[0] == t && e[1] == p && e[2] == nmax && e[3] == problems) return (int)e[4];
+    return h->variant;
 }
 
 // kind 0: eigenvalues of the matrices only; kind 1: matrices and all minors;
 // kind 2: one matrix and a subset of minors.
-eeid_status_t run_eigs(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64_t count, const int64_t *n,
-                       const int64_t *a_offset, const void *A, double *lambda, double *mu,
-                       int32_t *flags, int kind, int64_t nsel, const int64_t *js) {
+eeid_status_t prepare_eigs(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64_t count, const int64_t *n,
+                           const int64_t *a_offset, const void *A, double *lambda, double *mu, int32_t *flags,
+                           int kind, int64_t nsel, const int64_t *js, Enqueue *out, int *variant_used = nullptr) {
     using eeid::Item;
     HIP_TRY(h, hipSetDevice(h->device));
-    eeid_status_t s = upload_desc(h, count, n, a_offset);
+    eeid_status_t s = upload_desc(h, h->desc, h->desc_key, count, n, a_offset, -1);
     if (s != EEID_OK) return s;
-    const eeid::BatchDesc *desc = reinterpret_cast<const eeid::BatchDesc *>(h->desc.p);
-    std::vector<int64_t> key;
-    key.push_back(kind);
-    key.push_back((int64_t)t);
-    key.push_back((int64_t)p);
-    key.push_back((int64_t)(intptr_t)A);
-    key.push_back((int64_t)(intptr_t)lambda);
-    key.push_back((int64_t)(intptr_t)mu);
-    key.push_back(count);
-    for (int64_t b = 0; b < count; ++b) { key.push_back(n[b]); key.push_back(a_offset[b]); }
-    for (int64_t q = 0; q < nsel; ++q) key.push_back(js[q]);
 
     std::vector<Item> items;
     int64_t nmax = 0, lam = 0, muo = 0;
@@ -240,14 +233,179 @@ eeid_status_t run_eigs(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64_t c
     }
     // largest problems first so that the tail of the queue is short
     std::stable_sort(items.begin(), items.end(), [](const Item &x, const Item &y) { return x.m > y.m; });
+    std::vector<int64_t> ikey;
+    ikey.reserve(4 * items.size() + 1);
+    ikey.push_back((int64_t)items.size());
+    for (const Item &it : items) {
+        ikey.push_back((int64_t)(intptr_t)it.src);
+        ikey.push_back((int64_t)(intptr_t)it.out);
+        ikey.push_back(((int64_t)it.n << 32) | (uint32_t)it.j);
+        ikey.push_back(((int64_t)it.m << 32) | (uint32_t)it.b);
+    }
+    s = upload_table(h, h->items, h->items_key, ikey, items);
+    if (s != EEID_OK) return s;
+    h->n_items = (int64_t)items.size();
 
-    const int64_t nn_blocks = (nmax * nmax + 4095) / 4096;
-    hipLaunchKernelGGL(eeid::prep_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, h->stream,
-                       flags, count, (int *)nullptr);
-    hipLaunchKernelGGL(eeid::nonfinite_kernel, dim3((unsigned)nn_blocks, (unsigned)count), dim3(256), 0,
-                       h->stream, desc, Ad, t == EEID_C128 ? 1 : 0, flags);
-    HIP_TRY(h, hipGetLastError());
-    return dispatch_variant(h, t, p, items, key, (int)nmax, flags);
+    const int LDmax = (int)(((nmax + eeid::TILE - 1) / eeid::TILE) * eeid::TILE);
+    const int variant = pick_variant(h, t, p, nmax, (int64_t)items.size());
+    if (variant_used) *variant_used = variant;
+    const KernelChoice kc = choose_kernel(t, p, variant, LDmax);
+    HIP_TRY(h, hipFuncSetAttribute(kc.kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kc.lds));
+    int per_cu = 0;
+    HIP_TRY(h, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kc.kern, kc.nt, kc.lds));
+    if (per_cu < 1) return fail(h, EEID_ERR_UNSUPPORTED, "eigenvalue kernel cannot be resident");
+    int64_t slots = (int64_t)per_cu * h->cu_count;
+    slots = std::min<int64_t>(slots, std::max<int64_t>((int64_t)items.size(), 1));
+    size_t free_b = 0, total_b = 0;
+    HIP_TRY(h, hipMemGetInfo(&free_b, &total_b));
+    const size_t budget = (size_t)((double)(free_b + h->work.bytes) * 0.85);
+    slots = std::min<int64_t>(slots, (int64_t)(budget / (size_t)kc.slot));
+    if (slots < 1) return fail(h, EEID_ERR_ALLOC, "not enough device memory for one problem slot");
+    s = ensure(h, h->work, (size_t)(slots * kc.slot));
+    if (s != EEID_OK) return s;
+
+    eeid::TriArgs a;
+    a.items = reinterpret_cast<const Item *>(h->items.p);
+    a.n_items = h->n_items;
+    a.counter = h->counter;
+    a.flags = flags;
+    a.work = reinterpret_cast<char *>(h->work.p);
+    a.slot_bytes = kc.slot;
+    a.LDmax = LDmax;
+    const eeid::BatchDesc *desc = reinterpret_cast<const eeid::BatchDesc *>(h->desc.p);
+    const unsigned nn_blocks = (unsigned)((nmax * nmax + 4095) / 4096);
+    const int cplx = (t == EEID_C128) ? 1 : 0;
+    int *counter = h->counter;
+    const bool any_items = !items.empty();
+    *out = [=](hipStream_t st) -> hipError_t {
+        hipLaunchKernelGGL(eeid::prep_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, flags, count,
+                           (int *)nullptr);
+        hipLaunchKernelGGL(eeid::nonfinite_kernel, dim3(nn_blocks, (unsigned)count), dim3(256), 0, st, desc, Ad,
+                           cplx, flags);
+        if (!any_items) return hipGetLastError();
+        hipLaunchKernelGGL(eeid::reset_counter_kernel, dim3(1), dim3(64), 0, st, counter);
+        eeid::TriArgs args = a;
+        void *argv[] = {&args};
+        hipError_t e = hipLaunchKernel(kc.kern, dim3((unsigned)slots), dim3((unsigned)kc.nt), argv, kc.lds, st);
+        if (e != hipSuccess) return e;
+        return hipGetLastError();
+    };
+    return EEID_OK;
+}
+
+// Eq. (2) for the columns described by the descriptors in desc_buf.
+eeid_status_t prepare_identity(eeid_handle_t h, Buf &desc_buf, Buf &dpair_buf, int64_t count, int64_t nmax,
+                               int64_t ncol_max, int64_t ntot, const double *lambda, const double *mu, double *V2,
+                               int32_t *flags, Enqueue *out) {
+    eeid_status_t s = ensure(h, dpair_buf, sizeof(double) * 2 * (size_t)std::max<int64_t>(ntot, 1));
+    if (s != EEID_OK) return s;
+    const eeid::BatchDesc *desc = reinterpret_cast<const eeid::BatchDesc *>(desc_buf.p);
+    double *dpair = reinterpret_cast<double *>(dpair_buf.p);
+    const unsigned ib = (unsigned)((nmax + 255) / 256);
+    const unsigned jb = (unsigned)((ncol_max + eeid::ID_JT - 1) / eeid::ID_JT);
+    *out = [=](hipStream_t st) -> hipError_t {
+        hipLaunchKernelGGL(eeid::denominators_kernel, dim3(ib, (unsigned)count), dim3(256), 0, st, desc, lambda,
+                           dpair, flags);
+        hipLaunchKernelGGL(eeid::identity_kernel, dim3(ib, jb, (unsigned)count), dim3(256), 0, st, desc, lambda, mu,
+                           dpair, V2);
+        return hipGetLastError();
+    };
+    return EEID_OK;
+}
+
+eeid_status_t prepare_components(eeid_handle_t h, int64_t count, const int64_t *n, const double *lambda,
+                                 const double *mu, double *V2, int32_t *flags, Enqueue *out) {
+    if (count < 1) return fail(h, EEID_ERR_INVALID_ARG, "count must be >= 1");
+    if (!n || !lambda || !V2 || !flags) return fail(h, EEID_ERR_INVALID_ARG, "null pointer argument");
+    int64_t nmax = 0, ntot = 0;
+    bool need_mu = false;
+    for (int64_t b = 0; b < count; ++b) {
+        if (n[b] < 1) return fail(h, EEID_ERR_INVALID_ARG, "n[" + std::to_string(b) + "] must be >= 1");
+        if (n[b] > EEID_MAX_N_R64) return fail(h, EEID_ERR_UNSUPPORTED, "n exceeds the supported maximum");
+        nmax = std::max(nmax, n[b]);
+        ntot += n[b];
+        need_mu = need_mu || n[b] >= 2;
+    }
+    if (need_mu && !mu) return fail(h, EEID_ERR_INVALID_ARG, "mu is null");
+    HIP_TRY(h, hipSetDevice(h->device));
+    // a_offset does not matter here: keep the cached descriptors when the orders match
+    std::vector<int64_t> aoff(count, 0);
+    if (h->desc_key.size() == (size_t)(2 * count + 2) && h->desc_key[0] == count && h->desc_key[1] == -1) {
+        bool same = true;
+        for (int64_t b = 0; b < count && same; ++b) same = h->desc_key[2 + 2 * b] == n[b];
+        if (same)
+            for (int64_t b = 0; b < count; ++b) aoff[b] = h->desc_key[3 + 2 * b];
+    }
+    eeid_status_t s = upload_desc(h, h->desc, h->desc_key, count, n, aoff.data(), -1);
+    if (s != EEID_OK) return s;
+    return prepare_identity(h, h->desc, h->dpair, count, nmax, nmax, ntot, lambda, mu, V2, flags, out);
+}
+
+eeid_status_t run_now(eeid_handle_t h, const Enqueue &e) {
+    HIP_TRY(h, e(h->stream));
+    return EEID_OK;
+}
+
+// Record (once per key) and replay the enqueue steps as one hipGraph on the
+// handle's private stream, ordered after and before the caller's stream.
+eeid_status_t run_graph(eeid_handle_t h, const std::vector<int64_t> &key, const std::vector<Enqueue> &steps) {
+    if (!h->gstream) {
+        HIP_TRY(h, hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
+        HIP_TRY(h, hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
+        HIP_TRY(h, hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming));
+    }
+    if (!h->gexec || key != h->gkey) {
+        if (h->gexec) {
+            HIP_TRY(h, hipStreamSynchronize(h->gstream));
+            HIP_TRY(h, hipGraphExecDestroy(h->gexec));
+            h->gexec = nullptr;
+        }
+        hipGraph_t g = nullptr;
+        HIP_TRY(h, hipStreamBeginCapture(h->gstream, hipStreamCaptureModeThreadLocal));
+        hipError_t err = hipSuccess;
+        for (const Enqueue &e : steps)
+            if (err == hipSuccess) err = e(h->gstream);
+        hipError_t err2 = hipStreamEndCapture(h->gstream, &g);
+        if (err != hipSuccess || err2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(h, EEID_ERR_HIP, std::string("graph capture failed: ") +
+                                             hipGetErrorString(err != hipSuccess ? err : err2));
+        }
+        hipError_t err3 = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (err3 != hipSuccess) {
+            h->gexec = nullptr;
+            return fail(h, EEID_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(err3));
+        }
+        h->gkey = key;
+    }
+    HIP_TRY(h, hipEventRecord(h->ev_in, h->stream));
+    HIP_TRY(h, hipStreamWaitEvent(h->gstream, h->ev_in, 0));
+    HIP_TRY(h, hipGraphLaunch(h->gexec, h->gstream));
+    HIP_TRY(h, hipEventRecord(h->ev_out, h->gstream));
+    HIP_TRY(h, hipStreamWaitEvent(h->stream, h->ev_out, 0));
+    return EEID_OK;
+}
+
+void load_tune_table(eeid_handle_t h) {
+    const char *path = getenv("EEID_TUNE_TABLE");
+    if (!path || !*path) return;
+    h->tune_path = path;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    char line[256];
+    while (fgets(line, sizeof line, f)) {
+        long long a[5];
+        if (line[0] == '#') continue;
+        if (sscanf(line, "%lld %lld %lld %lld %lld", &a[0], &a[1], &a[2], &a[3], &a[4]) == 5 && a[4] >= 0 &&
+            a[4] < N_REAL_VARIANTS) {
+            bool replaced = false;  // later lines win
+            for (auto &e : h->tune)
+                if (e[0] == a[0] && e[1] == a[1] && e[2] == a[2] && e[3] == a[3]) { e[4] = a[4]; replaced = true; }
+            if (!replaced) h->tune.push_back({a[0], a[1], a[2], a[3], a[4]});
+        }
+    }
+    fclose(f);
 }
 
 }  // namespace
@@ -266,7 +424,11 @@ eeid_status_t eeid_create(eeid_handle_t *out, int hip_device) {
     eeid_handle_t h = new (std::nothrow) eeid_handle_s();
     if (!h) return EEID_ERR_ALLOC;
     h->device = hip_device;
-    if (const char *e = getenv("EEID_VARIANT")) h->variant = atoi(e);
+    if (const char *e = getenv("EEID_VARIANT")) {
+        const int v = atoi(e);
+        if (v >= 0 && v < N_REAL_VARIANTS) h->forced_variant = v;
+    }
+    load_tune_table(h);
     if (hipSetDevice(hip_device) != hipSuccess ||
         hipDeviceGetAttribute(&h->cu_count, hipDeviceAttributeMultiprocessorCount, hip_device) != hipSuccess ||
         hipMalloc(&h->counter, sizeof(int)) != hipSuccess) {
@@ -282,7 +444,12 @@ eeid_status_t eeid_destroy(eeid_handle_t h) {
     if (!h) return EEID_ERR_INVALID_ARG;
     (void)hipSetDevice(h->device);
     (void)hipStreamSynchronize(h->stream);
-    Buf *bufs[] = {&h->work, &h->items, &h->desc, &h->dpair, &h->flags1};
+    if (h->gstream) (void)hipStreamSynchronize(h->gstream);
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->ev_in) (void)hipEventDestroy(h->ev_in);
+    if (h->ev_out) (void)hipEventDestroy(h->ev_out);
+    if (h->gstream) (void)hipStreamDestroy(h->gstream);
+    Buf *bufs[] = {&h->work, &h->items, &h->desc, &h->desc_sub, &h->dpair, &h->dpair_sub};
     for (Buf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (h->counter) (void)hipFree(h->counter);
@@ -293,6 +460,12 @@ eeid_status_t eeid_destroy(eeid_handle_t h) {
 eeid_status_t eeid_set_stream(eeid_handle_t h, void *stream) {
     if (!h) return EEID_ERR_INVALID_ARG;
     h->stream = reinterpret_cast<hipStream_t>(stream);
+    return EEID_OK;
+}
+
+eeid_status_t eeid_set_graph_mode(eeid_handle_t h, int enable) {
+    if (!h) return EEID_ERR_INVALID_ARG;
+    h->graph_mode = (enable != 0);
     return EEID_OK;
 }
 
@@ -311,24 +484,28 @@ const char *eeid_status_string(eeid_status_t s) {
 const char *eeid_last_error(eeid_handle_t h) { return h ? h->err.c_str() : ""; }
 
 eeid_status_t eeid_eigvalsh_batched(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64_t count,
-                                    const int64_t *n, const int64_t *a_offset, const void *A,
-                                    double *lambda, int32_t *flags) {
+                                    const int64_t *n, const int64_t *a_offset, const void *A, double *lambda,
+                                    int32_t *flags) {
     eeid_status_t s = check_batch(h, t, p, count, n, a_offset, A);
     if (s != EEID_OK) return s;
     if (!lambda || !flags) return fail(h, EEID_ERR_INVALID_ARG, "null output pointer");
-    return run_eigs(h, t, p, count, n, a_offset, A, lambda, nullptr, flags, 0, 0, nullptr);
+    Enqueue e;
+    s = prepare_eigs(h, t, p, count, n, a_offset, A, lambda, nullptr, flags, 0, 0, nullptr, &e);
+    return s != EEID_OK ? s : run_now(h, e);
 }
 
 eeid_status_t eeid_minor_eigvals(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64_t count,
-                                 const int64_t *n, const int64_t *a_offset, const void *A,
-                                 double *lambda, double *mu, int32_t *flags) {
+                                 const int64_t *n, const int64_t *a_offset, const void *A, double *lambda,
+                                 double *mu, int32_t *flags) {
     eeid_status_t s = check_batch(h, t, p, count, n, a_offset, A);
     if (s != EEID_OK) return s;
     if (!lambda || !flags) return fail(h, EEID_ERR_INVALID_ARG, "null output pointer");
     bool need_mu = false;
     for (int64_t b = 0; b < count; ++b) need_mu = need_mu || n[b] >= 2;
     if (need_mu && !mu) return fail(h, EEID_ERR_INVALID_ARG, "mu is null");
-    return run_eigs(h, t, p, count, n, a_offset, A, lambda, mu, flags, 1, 0, nullptr);
+    Enqueue e;
+    s = prepare_eigs(h, t, p, count, n, a_offset, A, lambda, mu, flags, 1, 0, nullptr, &e);
+    return s != EEID_OK ? s : run_now(h, e);
 }
 
 eeid_status_t eeid_minor_eigvals_subset(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64_t n,
@@ -342,56 +519,116 @@ eeid_status_t eeid_minor_eigvals_subset(eeid_handle_t h, eeid_dtype_t t, eeid_pr
     if (n >= 2 && !mu_sel) return fail(h, EEID_ERR_INVALID_ARG, "mu_sel is null");
     for (int64_t q = 0; q < nsel; ++q)
         if (js[q] < 0 || js[q] >= n) return fail(h, EEID_ERR_INVALID_ARG, "js entry out of range");
-    return run_eigs(h, t, p, 1, &n, &zero, A, lambda, mu_sel, flag, 2, nsel, js);
+    Enqueue e;
+    s = prepare_eigs(h, t, p, 1, &n, &zero, A, lambda, mu_sel, flag, 2, nsel, js, &e);
+    return s != EEID_OK ? s : run_now(h, e);
 }
 
 eeid_status_t eeid_components(eeid_handle_t h, int64_t count, const int64_t *n, const double *lambda,
                               const double *mu, double *V2, int32_t *flags) {
     if (!h) return EEID_ERR_INVALID_ARG;
-    if (count < 1) return fail(h, EEID_ERR_INVALID_ARG, "count must be >= 1");
-    if (!n || !lambda || !V2 || !flags) return fail(h, EEID_ERR_INVALID_ARG, "null pointer argument");
-    int64_t nmax = 0, ntot = 0;
-    bool need_mu = false;
-    for (int64_t b = 0; b < count; ++b) {
-        if (n[b] < 1) return fail(h, EEID_ERR_INVALID_ARG, "n[" + std::to_string(b) + "] must be >= 1");
-        if (n[b] > EEID_MAX_N_R64) return fail(h, EEID_ERR_UNSUPPORTED, "n exceeds the supported maximum");
-        nmax = std::max(nmax, n[b]);
-        ntot += n[b];
-        need_mu = need_mu || n[b] >= 2;
-    }
-    if (need_mu && !mu) return fail(h, EEID_ERR_INVALID_ARG, "mu is null");
+    Enqueue e;
+    eeid_status_t s = prepare_components(h, count, n, lambda, mu, V2, flags, &e);
+    return s != EEID_OK ? s : run_now(h, e);
+}
+
+eeid_status_t eeid_components_subset(eeid_handle_t h, int64_t n, const double *lambda, int64_t nsel,
+                                     const double *mu_sel, double *V2_sel, int32_t *flag) {
+    if (!h) return EEID_ERR_INVALID_ARG;
+    if (n < 1 || n > EEID_MAX_N_R64) return fail(h, EEID_ERR_INVALID_ARG, "n out of range");
+    if (nsel < 1) return fail(h, EEID_ERR_INVALID_ARG, "nsel must be >= 1");
+    if (!lambda || !V2_sel || !flag || (n >= 2 && !mu_sel))
+        return fail(h, EEID_ERR_INVALID_ARG, "null pointer argument");
     HIP_TRY(h, hipSetDevice(h->device));
-    // descriptors: a_offset is irrelevant here; keep any cached one for the same n list
-    std::vector<int64_t> zeros(count, 0);
-    const int64_t *aoff = zeros.data();
-    if (h->desc_key.size() == (size_t)(2 * count + 1) && h->desc_key[0] == count) {
-        bool same = true;
-        for (int64_t b = 0; b < count && same; ++b) same = h->desc_key[1 + 2 * b] == n[b];
-        if (same)
-            for (int64_t b = 0; b < count; ++b) zeros[b] = h->desc_key[2 + 2 * b];
-    }
-    eeid_status_t s = upload_desc(h, count, n, aoff);
+    const int64_t zero = 0;
+    eeid_status_t s = upload_desc(h, h->desc_sub, h->desc_sub_key, 1, &n, &zero, nsel);
     if (s != EEID_OK) return s;
-    s = ensure(h, h->dpair, sizeof(double) * 2 * (size_t)ntot);
-    if (s != EEID_OK) return s;
-    const eeid::BatchDesc *desc = reinterpret_cast<const eeid::BatchDesc *>(h->desc.p);
-    double *dpair = reinterpret_cast<double *>(h->dpair.p);
-    const unsigned ib = (unsigned)((nmax + 255) / 256);
-    hipLaunchKernelGGL(eeid::denominators_kernel, dim3(ib, (unsigned)count), dim3(256), 0, h->stream, desc,
-                       lambda, dpair, flags);
-    const unsigned jb = (unsigned)((nmax + eeid::ID_JT - 1) / eeid::ID_JT);
-    hipLaunchKernelGGL(eeid::identity_kernel, dim3(ib, jb, (unsigned)count), dim3(256), 0, h->stream, desc,
-                       lambda, mu, dpair, V2);
-    HIP_TRY(h, hipGetLastError());
-    return EEID_OK;
+    Enqueue e;
+    s = prepare_identity(h, h->desc_sub, h->dpair_sub, 1, n, nsel, n, lambda, mu_sel, V2_sel, flag, &e);
+    return s != EEID_OK ? s : run_now(h, e);
 }
 
 eeid_status_t eeid_all_components(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64_t count,
                                   const int64_t *n, const int64_t *a_offset, const void *A, double *lambda,
                                   double *mu, double *V2, int32_t *flags) {
-    eeid_status_t s = eeid_minor_eigvals(h, t, p, count, n, a_offset, A, lambda, mu, flags);
+    eeid_status_t s = check_batch(h, t, p, count, n, a_offset, A);
     if (s != EEID_OK) return s;
-    return eeid_components(h, count, n, lambda, mu, V2, flags);
+    if (!lambda || !flags || !V2) return fail(h, EEID_ERR_INVALID_ARG, "null output pointer");
+    bool need_mu = false;
+    for (int64_t b = 0; b < count; ++b) need_mu = need_mu || n[b] >= 2;
+    if (need_mu && !mu) return fail(h, EEID_ERR_INVALID_ARG, "mu is null");
+    Enqueue e1, e2;
+    int variant = 0;
+    s = prepare_eigs(h, t, p, count, n, a_offset, A, lambda, mu, flags, 1, 0, nullptr, &e1, &variant);
+    if (s != EEID_OK) return s;
+    s = prepare_components(h, count, n, lambda, mu, V2, flags, &e2);
+    if (s != EEID_OK) return s;
+    if (!h->graph_mode) {
+        s = run_now(h, e1);
+        return s != EEID_OK ? s : run_now(h, e2);
+    }
+    std::vector<int64_t> key = {(int64_t)t, (int64_t)p, count, (int64_t)(intptr_t)A, (int64_t)(intptr_t)lambda,
+                                (int64_t)(intptr_t)mu, (int64_t)(intptr_t)V2, (int64_t)(intptr_t)flags,
+                                (int64_t)h->generation, (int64_t)variant};
+    for (int64_t b = 0; b < count; ++b) { key.push_back(n[b]); key.push_back(a_offset[b]); }
+    return run_graph(h, key, {e1, e2});
+}
+
+eeid_status_t eeid_autotune(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64_t count, const int64_t *n,
+                            const int64_t *a_offset, const void *A, double *lambda, double *mu, int32_t *flags,
+                            int *best_variant, double *best_ms) {
+    eeid_status_t s = check_batch(h, t, p, count, n, a_offset, A);
+    if (s != EEID_OK) return s;
+    if (!lambda || !flags) return fail(h, EEID_ERR_INVALID_ARG, "null output pointer");
+    bool need_mu = false;
+    for (int64_t b = 0; b < count; ++b) need_mu = need_mu || n[b] >= 2;
+    if (need_mu && !mu) return fail(h, EEID_ERR_INVALID_ARG, "mu is null");
+    HIP_TRY(h, hipSetDevice(h->device));
+    int64_t nmax = 0, problems = 0;
+    for (int64_t b = 0; b < count; ++b) {
+        nmax = std::max(nmax, n[b]);
+        problems += 1 + (n[b] >= 2 ? n[b] : 0);
+    }
+    const int nvar = (t == EEID_C128) ? 1 : N_REAL_VARIANTS;
+    hipEvent_t e0, e1;
+    HIP_TRY(h, hipEventCreate(&e0));
+    HIP_TRY(h, hipEventCreate(&e1));
+    const int saved = h->forced_variant;
+    int best = -1;
+    float best_t = 0.f;
+    for (int v = 0; v < nvar; ++v) {
+        h->forced_variant = v;
+        Enqueue e;
+        s = prepare_eigs(h, t, p, count, n, a_offset, A, lambda, mu, flags, 1, 0, nullptr, &e);
+        if (s != EEID_OK) break;
+        if (hipEventRecord(e0, h->stream) != hipSuccess || e(h->stream) != hipSuccess ||
+            hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            s = fail(h, EEID_ERR_HIP, "autotune launch failed");
+            break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (best < 0 || ms < best_t) { best = v; best_t = ms; }
+    }
+    h->forced_variant = saved;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s != EEID_OK) return s;
+    const std::array<int64_t, 5> entry = {(int64_t)t, (int64_t)p, nmax, problems, (int64_t)best};
+    bool replaced = false;
+    for (auto &e : h->tune)
+        if (e[0] == entry[0] && e[1] == entry[1] && e[2] == entry[2] && e[3] == entry[3]) { e = entry; replaced = true; }
+    if (!replaced) h->tune.push_back(entry);
+    if (!h->tune_path.empty()) {
+        if (FILE *f = fopen(h->tune_path.c_str(), "a")) {
+            fprintf(f, "%lld %lld %lld %lld %d  # %s %.3f ms\n", (long long)t, (long long)p, (long long)nmax,
+                    (long long)problems, best, t == EEID_C128 ? "complex" : VARIANT_NAME[best], best_t);
+            fclose(f);
+        }
+    }
+    if (best_variant) *best_variant = best;
+    if (best_ms) *best_ms = best_t;
+    return EEID_OK;
 }
 
 }  // extern "C"

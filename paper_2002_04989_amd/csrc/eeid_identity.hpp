@@ -19,10 +19,10 @@ namespace eeid {
 struct BatchDesc {
     int64_t a_off;    // element offset of the matrix in A
     int64_t lam_off;  // offset of its n eigenvalues in lambda
-    int64_t mu_off;   // offset of its n (n - 1) minor eigenvalues in mu
-    int64_t v2_off;   // offset of its n^2 components in V2
+    int64_t mu_off;   // offset of its ncol (n - 1) minor eigenvalues in mu
+    int64_t v2_off;   // offset of its n * ncol components in V2 (row i: ncol values)
     int32_t n;
-    int32_t pad;
+    int32_t ncol;     // minors (columns) given: n for all of them, fewer for a subset
 };
 
 __device__ __forceinline__ void neumaier_add(double &s, double &c, double x) {
@@ -99,14 +99,16 @@ __global__ __launch_bounds__(256) void denominators_kernel(const BatchDesc *desc
 constexpr int ID_JT = 8;    // minors (columns j) per thread
 constexpr int ID_KC = 256;  // minor eigenvalues staged per LDS chunk
 
-// V2[v2_off + i*n + j] for i in a 256-block (blockIdx.x) and j in an ID_JT-block (blockIdx.y).
+// V2[v2_off + i*ncol + j] for i in a 256-block (blockIdx.x) and j in an ID_JT-block (blockIdx.y):
+// column j is the minor whose spectrum is row j of mu (all minors: ncol = n).
 __global__ __launch_bounds__(256) void identity_kernel(const BatchDesc *desc, const double *lambda,
                                                         const double *mu, const double *Dpair, double *V2) {
     __shared__ double sm[ID_JT][ID_KC];
     const int b = blockIdx.z;
     const int n = desc[b].n;
+    const int ncol = desc[b].ncol;
     const int j0 = blockIdx.y * ID_JT;
-    if (j0 >= n || (int)blockIdx.x * 256 >= n) return;
+    if (j0 >= ncol || (int)blockIdx.x * 256 >= n) return;
     const int m = n - 1;
     const int i = blockIdx.x * 256 + threadIdx.x;
     const bool live = i < n;
@@ -122,7 +124,7 @@ __global__ __launch_bounds__(256) void identity_kernel(const BatchDesc *desc, co
         for (int q = threadIdx.x; q < ID_JT * ID_KC; q += 256) {
             const int jj = q / ID_KC, kk = q % ID_KC;
             const int j = j0 + jj;
-            sm[jj][kk] = (j < n && kk < kn) ? mub[(int64_t)j * m + kc + kk] : 0.0;
+            sm[jj][kk] = (j < ncol && kk < kn) ? mub[(int64_t)j * m + kc + kk] : 0.0;
         }
         __syncthreads();
         for (int kk = 0; kk < kn; ++kk) {
@@ -137,11 +139,11 @@ __global__ __launch_bounds__(256) void identity_kernel(const BatchDesc *desc, co
     if (!live) return;
     const double *dp = Dpair + 2 * (desc[b].lam_off + i);
     const double dhi = dp[0], dlo = dp[1];
-    double *out = V2 + desc[b].v2_off + (int64_t)i * n;
+    double *out = V2 + desc[b].v2_off + (int64_t)i * ncol;
 #pragma unroll
     for (int t = 0; t < ID_JT; ++t) {
         const int j = j0 + t;
-        if (j >= n) break;
+        if (j >= ncol) break;
         double w;
         if (isnan(dhi)) w = __builtin_nan("");
         else if (zero[t]) w = 0.0;

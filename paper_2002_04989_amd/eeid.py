@@ -24,8 +24,10 @@ STATUS = {0: "EEID_OK", 1: "EEID_ERR_INVALID_ARG", 2: "EEID_ERR_NO_DEVICE", 3: "
 EXPORTS = (
     "eeid_create", "eeid_destroy", "eeid_set_stream", "eeid_status_string", "eeid_last_error",
     "eeid_eigvalsh_batched", "eeid_minor_eigvals", "eeid_minor_eigvals_subset",
-    "eeid_components", "eeid_all_components",
+    "eeid_components", "eeid_components_subset", "eeid_all_components", "eeid_set_graph_mode",
+    "eeid_autotune",
 )
+VARIANTS = ("nb32_nt512", "nb32_nt256x2", "nb16_nt512")
 
 
 class EEIDError(RuntimeError):
@@ -63,6 +65,10 @@ def load_library(path: str = LIB_PATH):
                                               _vp, _vp, _vp]
     lib.eeid_components.argtypes = [_vp, ctypes.c_int64, _i64p, _vp, _vp, _vp, _vp]
     lib.eeid_all_components.argtypes = [_vp, c, c, ctypes.c_int64, _i64p, _i64p, _vp, _vp, _vp, _vp, _vp]
+    lib.eeid_components_subset.argtypes = [_vp, ctypes.c_int64, _vp, ctypes.c_int64, _vp, _vp, _vp]
+    lib.eeid_set_graph_mode.argtypes = [_vp, c]
+    lib.eeid_autotune.argtypes = [_vp, c, c, ctypes.c_int64, _i64p, _i64p, _vp, _vp, _vp, _vp,
+                                  ctypes.POINTER(c), ctypes.POINTER(ctypes.c_double)]
     for name in EXPORTS:
         if name not in ("eeid_status_string", "eeid_last_error"):
             getattr(lib, name).restype = ctypes.c_int
@@ -187,6 +193,47 @@ def components(lam, mu, n: Sequence[int], flags):
                                            mu.data_ptr() if mu.numel() else None, V2.data_ptr(),
                                            flags.data_ptr()), h)
     return V2
+
+
+def components_subset(lam, mu_sel, flag):
+    """Columns of Eq. (2) for selected minors of one matrix: W_sel [n, nsel], W_sel[i, s] = |v_i(j_s)|^2."""
+    import torch
+    n = int(lam.numel())
+    nsel = int(mu_sel.shape[0])
+    V2 = torch.empty((n, nsel), dtype=torch.float64, device=lam.device)
+    h = handle(lam.device.index)
+    mu_c = mu_sel.contiguous()
+    _check(load_library().eeid_components_subset(h, n, lam.data_ptr(), nsel,
+                                                  mu_c.data_ptr() if mu_c.numel() else None, V2.data_ptr(),
+                                                  flag.data_ptr()), h)
+    return V2
+
+
+def set_graph_mode(enable: bool, device: int | None = None):
+    """Record eeid_all_components into a hipGraph per argument set and replay it."""
+    h = handle(device)
+    _check(load_library().eeid_set_graph_mode(h, 1 if enable else 0), h)
+
+
+def autotune(mats, prec: str = "fp64"):
+    """Time every kernel configuration on this batch; the fastest is used from then on.
+
+    Returns (variant name, milliseconds)."""
+    import torch
+    flat, n, offs = _batch(mats)
+    dev = flat.device
+    nl, nm, _ = sizes(n)
+    lam = torch.empty(nl, dtype=torch.float64, device=dev)
+    mu = torch.empty(max(nm, 1), dtype=torch.float64, device=dev)
+    flags = torch.empty(len(n), dtype=torch.int32, device=dev)
+    best = ctypes.c_int(-1)
+    ms = ctypes.c_double(0.0)
+    h = handle(dev.index)
+    _check(load_library().eeid_autotune(h, _dtype_code(flat), PREC[prec], len(n), _i64(n), _i64(offs),
+                                         flat.data_ptr(), lam.data_ptr(), mu.data_ptr(), flags.data_ptr(),
+                                         ctypes.byref(best), ctypes.byref(ms)), h)
+    name = "complex" if _dtype_code(flat) == C128 else VARIANTS[best.value]
+    return name, ms.value
 
 
 def all_components(mats, prec: str = "fp64"):

@@ -230,3 +230,68 @@ def test_c64_trailing_form_error_is_bounded():
     assert dl < 8 * np.sqrt(n) * 2.0 ** -24 and dm < 8 * np.sqrt(n) * 2.0 ** -24
     assert dw < 1e-2
     assert flag == 0
+
+
+# ------------------------------------------------------------ partial queries, graph mode, autotuning
+def test_components_subset_matches_full_columns():
+    import torch
+    from paper_2002_04989_amd import eeid
+    n = 150
+    announce(f"components subset n={n}")
+    A = inputs.goe(n, 21)
+    js = [0, 7, 149, 7]
+    dA = torch.from_numpy(A).cuda()
+    lam, mu, flag = eeid.minor_eigvals_subset(dA, js)
+    Wsel = eeid.components_subset(lam, mu, flag).cpu().numpy()
+    lam_o, mu_o, W_o, _ = oracle.components_identity(A, js=js)
+    np.testing.assert_allclose(Wsel, W_o, atol=W_TOL, rtol=0)
+    lam_f, mu_f, W_f, _ = run_all([A])[0]
+    np.testing.assert_allclose(Wsel, W_f[:, js], atol=1e-13, rtol=0)
+    assert int(flag.cpu()[0]) == 0
+
+
+def test_graph_mode_replays_match_eager():
+    import torch
+    from paper_2002_04989_amd import eeid
+    mats = [inputs.goe(96, 5), inputs.wishart(70, 6), inputs.goe(1, 7)]
+    announce("graph mode replays")
+    dev = [torch.from_numpy(m).cuda() for m in mats]
+    eeid.set_graph_mode(False)
+    ref = [t.cpu().numpy() for t in eeid.all_components(dev, "fp64")]
+    eeid.set_graph_mode(True)
+    try:
+        flat, n, offs = eeid._batch(dev)
+        nl, nm, nv = eeid.sizes(n)
+        lam = torch.empty(nl, dtype=torch.float64, device="cuda")
+        mu = torch.empty(nm, dtype=torch.float64, device="cuda")
+        V2 = torch.empty(nv, dtype=torch.float64, device="cuda")
+        flags = torch.empty(len(n), dtype=torch.int32, device="cuda")
+        lib = eeid.load_library()
+        for rep in range(3):
+            h = eeid.handle()
+            st = lib.eeid_all_components(h, 0, 0, len(n), eeid._i64(n), eeid._i64(offs), flat.data_ptr(),
+                                         lam.data_ptr(), mu.data_ptr(), V2.data_ptr(), flags.data_ptr())
+            assert st == 0, lib.eeid_last_error(h)
+            torch.cuda.synchronize()
+            got = [lam.cpu().numpy(), mu.cpu().numpy(), V2.cpu().numpy(), flags.cpu().numpy()]
+            for x, y in zip(got[:3], ref[:3]):
+                np.testing.assert_allclose(x, y, atol=1e-12, rtol=0)
+            np.testing.assert_array_equal(got[3], ref[3])
+            # eager work between replays, and clobbered outputs
+            lam.fill_(-7.0); V2.zero_(); mu.fill_(3.0)
+            _ = eeid.eigvalsh_batched(dev[0])
+            torch.cuda.synchronize()
+    finally:
+        eeid.set_graph_mode(False)
+
+
+def test_autotune_picks_a_variant_and_results_hold():
+    from paper_2002_04989_amd import eeid
+    mats = [inputs.goe(130, 8), inputs.goe(64, 9)]
+    announce("autotune")
+    import torch
+    dev = [torch.from_numpy(m).cuda() for m in mats]
+    name, ms = eeid.autotune(dev, "fp64")
+    assert name in eeid.VARIANTS and ms > 0
+    for A, got in zip(mats, run_all(mats)):
+        check(A, got)
