@@ -54,6 +54,7 @@ struct eeid_handle_s {
     int64_t n_items = 0;
     int variant = 0;            // real-kernel configuration when the tune table has no entry
     int forced_variant = -1;    // >= 0: use this configuration (autotuning, EEID_VARIANT)
+    int64_t max_slots = 0;      // > 0: cap on resident problems (EEID_MAX_SLOTS)
     uint64_t generation = 0;    // bumped whenever a buffer the kernels read is reallocated or rewritten
     // graph mode
     bool graph_mode = false;
@@ -255,6 +256,7 @@ eeid_status_t prepare_eigs(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64
     HIP_TRY(h, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kc.kern, kc.nt, kc.lds));
     if (per_cu < 1) return fail(h, EEID_ERR_UNSUPPORTED, "eigenvalue kernel cannot be resident");
     int64_t slots = (int64_t)per_cu * h->cu_count;
+    if (h->max_slots > 0) slots = std::min<int64_t>(slots, h->max_slots);
     slots = std::min<int64_t>(slots, std::max<int64_t>((int64_t)items.size(), 1));
     size_t free_b = 0, total_b = 0;
     HIP_TRY(h, hipMemGetInfo(&free_b, &total_b));
@@ -428,6 +430,7 @@ eeid_status_t eeid_create(eeid_handle_t *out, int hip_device) {
         const int v = atoi(e);
         if (v >= 0 && v < N_REAL_VARIANTS) h->forced_variant = v;
     }
+    if (const char *e = getenv("EEID_MAX_SLOTS")) h->max_slots = atoll(e);
     load_tune_table(h);
     if (hipSetDevice(hip_device) != hipSuccess ||
         hipDeviceGetAttribute(&h->cu_count, hipDeviceAttributeMultiprocessorCount, hip_device) != hipSuccess ||

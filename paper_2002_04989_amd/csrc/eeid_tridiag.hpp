@@ -23,6 +23,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#ifndef EEID_NT_LOADS
+#define EEID_NT_LOADS 1
+#endif
+
 namespace eeid {
 
 constexpr int TILE = 64;
@@ -38,9 +42,23 @@ struct Item {
     int32_t b;          // batch index (flags)
 };
 
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+
 template <class S> struct Vec;
-template <> struct Vec<double> { static constexpr int W = 2; typedef double2 type; };
-template <> struct Vec<float> { static constexpr int W = 4; typedef float4 type; };
+template <> struct Vec<double> { static constexpr int W = 2; typedef dvec2 type; };
+template <> struct Vec<float> { static constexpr int W = 4; typedef fvec4 type; };
+
+// The stale trailing matrix is streamed exactly once per column: its loads
+// are non-temporal so they do not displace the panel (V, W) in the caches.
+template <class VT>
+__device__ __forceinline__ VT stream_load(const VT *p) {
+#if EEID_NT_LOADS
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
 
 __device__ __forceinline__ int64_t tile_index(int I, int J, int T) {
     return (int64_t)J * T - (int64_t)J * (J - 1) / 2 + (I - J);
@@ -349,7 +367,7 @@ struct Tri {
             VT buf[NV];
             if (live) {
 #pragma unroll
-                for (int q = 0; q < NV; ++q) buf[q] = *reinterpret_cast<const VT *>(tp + q * (TILE * VW) + lane * VW);
+                for (int q = 0; q < NV; ++q) buf[q] = stream_load(reinterpret_cast<const VT *>(tp + q * (TILE * VW) + lane * VW));
             } else {
 #pragma unroll
                 for (int q = 0; q < NV; ++q) buf[q] = VT{};
