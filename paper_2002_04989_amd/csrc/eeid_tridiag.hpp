@@ -188,7 +188,12 @@ __device__ void bisect_tridiagonal(const double *dg, const double *eg, int m, do
                 const double d = de[2 * i], e2 = de[2 * i + 1];
 #pragma unroll
                 for (int t = 0; t < ILP; ++t) {
-                    double v = (d - x[t]) - e2 / q[t];
+                    // e2 / q by the hardware reciprocal and two Newton steps (a few ulp;
+                    // |q| >= pivmin keeps e2 / q finite)
+                    double r = __builtin_amdgcn_rcp(q[t]);
+                    r = fma(fma(-q[t], r, 1.0), r, r);
+                    r = fma(fma(-q[t], r, 1.0), r, r);
+                    double v = (d - x[t]) - e2 * r;
                     v = (fabs(v) < pivmin) ? -pivmin : v;
                     cnt[t] += (v < 0.0) ? 1 : 0;
                     q[t] = v;
@@ -477,11 +482,13 @@ struct Tri {
 #pragma unroll
                     for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
-                        for (int g = 0; g < 4; ++g) c[jb][g] = tp[tile_off<S>(row, jb * 16 + lk + 4 * g)];
+                        for (int g = 0; g < 4; ++g)
+                            c[jb][g] = __builtin_nontemporal_load(&tp[tile_off<S>(row, jb * 16 + lk + 4 * g)]);
 #pragma unroll
                     for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
-                        for (int g = 0; g < 4; ++g) tp[tile_off<S>(row, jb * 16 + lk + 4 * g)] = c[jb][g] - acc[jb][ib][g];
+                        for (int g = 0; g < 4; ++g)
+                            __builtin_nontemporal_store(c[jb][g] - acc[jb][ib][g], &tp[tile_off<S>(row, jb * 16 + lk + 4 * g)]);
                 }
             } else {
                 flt4 acc[4][2];
@@ -517,16 +524,14 @@ struct Tri {
 #pragma unroll
                 for (int ib = 0; ib < 2; ++ib) {
                     const int row = (ip + ib) * 16 + lr;
-                    float4 c[4];
+                    fvec4 c[4];
 #pragma unroll
                     for (int jb = 0; jb < 4; ++jb)
-                        c[jb] = *reinterpret_cast<const float4 *>(tp + tile_off<S>(row, jb * 16 + 4 * lk));
+                        c[jb] = __builtin_nontemporal_load(reinterpret_cast<const fvec4 *>(tp + tile_off<S>(row, jb * 16 + 4 * lk)));
 #pragma unroll
-                    for (int jb = 0; jb < 4; ++jb) {
-                        c[jb].x -= acc[jb][ib][0]; c[jb].y -= acc[jb][ib][1];
-                        c[jb].z -= acc[jb][ib][2]; c[jb].w -= acc[jb][ib][3];
-                        *reinterpret_cast<float4 *>(tp + tile_off<S>(row, jb * 16 + 4 * lk)) = c[jb];
-                    }
+                    for (int jb = 0; jb < 4; ++jb)
+                        __builtin_nontemporal_store(c[jb] - acc[jb][ib],
+                                                    reinterpret_cast<fvec4 *>(tp + tile_off<S>(row, jb * 16 + 4 * lk)));
                 }
             }
         }
