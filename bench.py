@@ -48,16 +48,27 @@ def kernel_sources_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(form: str):
-    """HBM bytes per launch from the committed counter summary, if it matches these kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"tridiag_{form}_n2048x2_counters.json")
+# compiled configurations of the eigenvalue kernel (eeid.VARIANTS): panel width NB, threads per block NT
+VARIANT_SHAPE = {"nb32_nt512": (32, 512), "nb32_nt256x2": (32, 256), "nb16_nt512": (16, 512)}
+
+
+def kernel_name(form: str, variant: str) -> str:
+    nb, nt = VARIANT_SHAPE[variant]
+    s = "double" if form == "fp64" else "float"
+    return f"void eeid::tridiag_bisect_kernel<{s}, {nb}, {nt}, 32, true, 2>(eeid::TriArgs)"
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if it matches these sources."""
+    path = os.path.join(ROOT, "profiles", "tridiag_n2048x2_counters.json")
     try:
         d = json.load(open(path))
     except (OSError, ValueError):
         return None
     if d.get("kernel_sources_hash") != kernel_sources_hash():
         return None
-    return d.get("hbm_bytes_per_launch")
+    k = d.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("hbm_bytes_per_launch")
 
 
 def make_inputs():
@@ -234,10 +245,10 @@ def main():
     # per matrix: n minors of order n-1 plus A itself; two matrices per launch
     algo_bytes = 2 * (N * symv_bytes(N - 1, 8) + symv_bytes(N, 8))
     achieved = algo_bytes / (tri64 * 1e-3) / 1e9
-    traffic = measured_traffic("fp64")
+    kname64 = kernel_name("fp64", tuned64[0] if tuned64 else "nb32_nt512")
+    traffic = measured_traffic(kname64)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "tridiag_bisect_kernel<double,...> (" + (tuned64[0] if tuned64 else "nb32_nt512") + ")",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname64,
                 "kernel_ms_per_launch": round(tri64, 2), "identity_ms_per_launch": round(id64, 2),
                 "algorithmic_bytes_per_launch": algo_bytes}
 
@@ -248,15 +259,15 @@ def main():
                                                        not args.no_tune)
         h32 = [t.cpu().numpy() for t in res32]
         algo32 = 2 * (N * symv_bytes(N - 1, 4) + symv_bytes(N, 4))
+        kname32 = kernel_name("fp32", tuned32[0] if tuned32 else "nb32_nt512")
         ach32 = algo32 / (tri32 * 1e-3) / 1e9
         fp32 = {"value": comps / (wall32 / args.steps), "unit": "components/s",
                 "ms_per_step": round(wall32 / args.steps * 1e3, 2), "dtype": "f32 trailing matrix / f64 rest",
                 "speedup_vs_fp64": round((wall64 / wall32), 3),
                 "roofline": {"bound": "hbm", "achieved": round(ach32, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                             "frac": round(ach32 / HBM_PEAK_GBS, 4), "traffic": measured_traffic("fp32"),
-                             "kernel_ms_per_launch": round(tri32, 2),
-                             "kernel": "tridiag_bisect_kernel<float,...> (" + (tuned32[0] if tuned32 else "nb32_nt512")
-                                       + ")"},
+                             "frac": round(ach32 / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kname32),
+                             "kernel_ms_per_launch": round(tri32, 2), "kernel": kname32,
+                             "algorithmic_bytes_per_launch": algo32},
                 "errors_vs_oracle": errors(mats, truth, h32[0], h32[1], h32[2], n),
                 "flags": [int(x) for x in h32[3]]}
 

@@ -353,6 +353,10 @@ struct Tri {
     static constexpr int VW = Vec<S>::W;
     static constexpr int NV = CW / VW;  // 16-byte vectors per lane per tile
 
+    // Tiles loaded together per step: an FP32 tile row is half as many bytes,
+    // so two tiles keep as many bytes in flight per wave as one FP64 tile.
+    static constexpr int UT = (sizeof(S) == 4) ? 2 : 1;
+
     __device__ void symv_unit(int J, int h, int Ib, int Ie, int k) {
         const int c0 = J * TILE + h * CW;
         // Columns left of the trailing matrix are loaded too (one base address,
@@ -362,38 +366,54 @@ struct Tri {
         double pc[CW];
 #pragma unroll
         for (int c = 0; c < CW; ++c) pc[c] = 0.0;
-        for (int I = Ib; I < Ie; ++I) {
-            int uo = c0;
-            asm volatile("" : "+v"(uo));  // u(c0 .. c0+CW) is re-read from LDS, not held in registers
-            const double2 *uj2 = reinterpret_cast<const double2 *>(u + uo);
-            const S *tp = tile_ptr(I, J) + h * (CW * TILE);
-            const int row = I * TILE + lane;
-            const bool live = row > k;
-            VT buf[NV];
-            if (live) {
+        for (int I = Ib; I < Ie; I += UT) {
+            VT buf[UT][NV];
+            // Only the first tile of a step can hold rows <= k (tile J0); they
+            // are not loaded.  A missing last tile of a step re-reads the
+            // step's first tile and is not used.
+            // The unconditional loads go first: loads under the lane condition
+            // make the compiler wait for every outstanding load before any
+            // later load that reuses a register.
 #pragma unroll
-                for (int q = 0; q < NV; ++q) buf[q] = stream_load(reinterpret_cast<const VT *>(tp + q * (TILE * VW) + lane * VW));
+            for (int t = 1; t < UT; ++t) {
+                const S *tp = tile_ptr(min(I + t, Ie - 1), J) + h * (CW * TILE);
+#pragma unroll
+                for (int q = 0; q < NV; ++q) buf[t][q] = stream_load(reinterpret_cast<const VT *>(tp + q * (TILE * VW) + lane * VW));
+            }
+            const bool live0 = I * TILE + lane > k;
+            if (live0) {
+                const S *tp = tile_ptr(I, J) + h * (CW * TILE);
+#pragma unroll
+                for (int q = 0; q < NV; ++q) buf[0][q] = stream_load(reinterpret_cast<const VT *>(tp + q * (TILE * VW) + lane * VW));
             } else {
 #pragma unroll
-                for (int q = 0; q < NV; ++q) buf[q] = VT{};
+                for (int q = 0; q < NV; ++q) buf[0][q] = VT{};
             }
-            double s = 0.0;
 #pragma unroll
-            for (int q = 0; q < NV; ++q)
-#pragma unroll
-                for (int z = 0; z < VW; z += 2) {
-                    const double2 w = uj2[(q * VW + z) / 2];
-                    s = fma((double)buf[q][z], w.x, s);
-                    s = fma((double)buf[q][z + 1], w.y, s);
-                }
-            if (I != J) {
-                const double ui = u[row];
+            for (int t = 0; t < UT; ++t) {
+                if (t > 0 && I + t >= Ie) break;
+                int uo = c0;
+                asm volatile("" : "+v"(uo));  // u(c0 .. c0+CW) is re-read from LDS, not held in registers
+                const double2 *uj2 = reinterpret_cast<const double2 *>(u + uo);
+                const int row = (I + t) * TILE + lane;
+                double s = 0.0;
 #pragma unroll
                 for (int q = 0; q < NV; ++q)
 #pragma unroll
-                    for (int z = 0; z < VW; ++z) pc[q * VW + z] = fma((double)buf[q][z], ui, pc[q * VW + z]);
+                    for (int z = 0; z < VW; z += 2) {
+                        const double2 w = uj2[(q * VW + z) / 2];
+                        s = fma((double)buf[t][q][z], w.x, s);
+                        s = fma((double)buf[t][q][z + 1], w.y, s);
+                    }
+                if (I + t != J) {
+                    const double ui = u[row];
+#pragma unroll
+                    for (int q = 0; q < NV; ++q)
+#pragma unroll
+                        for (int z = 0; z < VW; ++z) pc[q * VW + z] = fma((double)buf[t][q][z], ui, pc[q * VW + z]);
+                }
+                if (t > 0 || live0) atomicAdd(&y[row], s);
             }
-            if (live) atomicAdd(&y[row], s);
         }
         if (Ie > Ib + (Ib == J ? 1 : 0)) {  // some off-diagonal tile contributed column sums
             constexpr int SH = (CW == 32) ? 1 : 2;
