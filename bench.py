@@ -43,18 +43,20 @@ def symv_bytes(m: int, s: int) -> int:
 
 def kernel_sources_hash() -> str:
     h = hashlib.sha256()
-    for f in ("eeid.hip", "eeid_tridiag.hpp", "eeid_tridiag_c.hpp", "eeid_identity.hpp"):
+    for f in ("eeid.hip", "eeid_tridiag.hpp", "eeid_tridiag_c.hpp", "eeid_band.hpp", "eeid_identity.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2002_04989_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
 # compiled configurations of the eigenvalue kernel (eeid.VARIANTS): panel width NB, threads per block NT
-VARIANT_SHAPE = {"nb32_nt512": (32, 512), "nb32_nt256x2": (32, 256), "nb16_nt512": (16, 512)}
+VARIANT_SHAPE = {"nb32_nt512": (32, 512), "nb32_nt256x2": (32, 256), "nb16_nt512": (16, 512), "band32_nt512": (32, 512)}
 
 
 def kernel_name(form: str, variant: str) -> str:
     nb, nt = VARIANT_SHAPE[variant]
     s = "double" if form == "fp64" else "float"
+    if variant.startswith("band"):
+        return f"void eeid::band_bisect_kernel<{s}, {nt}>(eeid::TriArgs)"
     return f"void eeid::tridiag_bisect_kernel<{s}, {nb}, {nt}, 32, true, 2>(eeid::TriArgs)"
 
 

@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "eeid.h"
+#include "eeid_band.hpp"
 #include "eeid_identity.hpp"
 #include "eeid_tridiag.hpp"
 #include "eeid_tridiag_c.hpp"
@@ -37,9 +38,10 @@ struct Buf {
 typedef std::function<hipError_t(hipStream_t)> Enqueue;
 
 // Compiled configurations of the real eigenvalue kernel (the complex kernel
-// has one): panel width NB and threads per workgroup.
-constexpr int N_REAL_VARIANTS = 3;
-const char *const VARIANT_NAME[N_REAL_VARIANTS] = {"nb32_nt512", "nb32_nt256x2", "nb16_nt512"};
+// has one): one-stage reduction with panel width NB and threads per
+// workgroup, or the two-stage (dense -> band -> tridiagonal) reduction.
+constexpr int N_REAL_VARIANTS = 4;
+const char *const VARIANT_NAME[N_REAL_VARIANTS] = {"nb32_nt512", "nb32_nt256x2", "nb16_nt512", "band32_nt512"};
 
 }  // namespace
 
@@ -180,6 +182,12 @@ KernelChoice real_kernel(int LDmax) {
             (size_t)lds_bytes_for<NB, NT, true>(LDmax)};
 }
 
+template <class S, int NT>
+KernelChoice band_kernel(int LDmax) {
+    using namespace eeid;
+    return {(const void *)band_bisect_kernel<S, NT>, NT, slot_bytes_band<S>(LDmax), (size_t)lds_bytes_band<NT>(LDmax)};
+}
+
 template <class R, int NB, int NT>
 KernelChoice complex_kernel(int LDmax) {
     using namespace eeid;
@@ -193,6 +201,7 @@ KernelChoice choose_kernel(eeid_dtype_t t, eeid_prec_t p, int variant, int LDmax
     switch (variant) {
         case 1: return d ? real_kernel<double, 32, 256>(LDmax) : real_kernel<float, 32, 256>(LDmax);
         case 2: return d ? real_kernel<double, 16, 512>(LDmax) : real_kernel<float, 16, 512>(LDmax);
+        case 3: return d ? band_kernel<double, 512>(LDmax) : band_kernel<float, 512>(LDmax);
         default: return d ? real_kernel<double, 32, 512>(LDmax) : real_kernel<float, 32, 512>(LDmax);
     }
 }

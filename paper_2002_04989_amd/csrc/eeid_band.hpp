@@ -1,0 +1,748 @@
+// Two-stage tridiagonalisation of real symmetric problems on gfx950, for the
+// EigenValues step of Algorithms 1 and 2 (Section 3 of the paper), applied to
+// A and to each principal minor M_j (Section 2).  One workgroup per problem,
+// persistent over the same queue as the one-stage kernel of eeid_tridiag.hpp.
+//
+//   stage 1, dense -> band of half-bandwidth BW: per panel of BW columns a
+//     Householder QR of the panel below the band (left-looking, compact WY
+//     form I - V T V^T), then the two-sided update of the trailing matrix
+//     A22 <- Q^T A22 Q = A22 - V W^T - W V^T with Y = A22 V (two MFMA passes
+//     over the stored lower triangle), X = Y T, W = X - 1/2 V (T^T V^T X);
+//   stage 2, band -> tridiagonal by Householder bulge chasing: sweep s removes
+//     column s below the subdiagonal; each step of a sweep applies the
+//     previous reflector from the right to the BW x BW block below it,
+//     annihilates the first column of the bulge this creates and applies the
+//     new reflector to the rest of that block and two-sidedly to the next
+//     diagonal block;
+//   then all eigenvalues of the tridiagonal by the Sturm bisection of the
+//   one-stage kernel.
+//
+// The one-stage reduction streams the whole trailing triangle from HBM once
+// per column; here it is read three times per panel of BW columns (two SYMM
+// passes and the read-modify-write of the update), so HBM traffic drops by
+// about BW / 4.  Both stages are orthogonal similarities, so the eigenvalues
+// are those of the problem up to backward-stable rounding.
+//
+// Trailing-matrix storage (S = double or float): the lower triangle in 64x64
+// tiles as in eeid_tridiag.hpp, but inside a tile 16x16 sub-blocks, sub-block
+// (sr, sc) at (sc * 4 + sr) * 256, column-major inside a sub-block: element
+// (r, c) at ((c / 16) * 4 + r / 16) * 256 + (c % 16) * 16 + r % 16.  Each
+// matrix-core operand then loads as 512 contiguous bytes (FP64).
+// Band storage: column c holds A(c + d, c), d in [0, 2 BW), at bnd[c * BLD + d]
+// (the chase leaves fill up to d = 2 BW - 1 during a step).
+#pragma once
+#include "eeid_tridiag.hpp"
+
+namespace eeid {
+
+constexpr int BW = 32;        // half-bandwidth of the intermediate band = panel width
+constexpr int BLD = 2 * BW;   // band storage per column
+
+__device__ __forceinline__ int mtile_off(int r, int c) {
+    return (((c >> 4) << 2) + (r >> 4)) * 256 + ((c & 15) << 4) + (r & 15);
+}
+
+template <class S, int NT>
+struct Band {
+    static constexpr int NWAVE = NT / 64;
+    static constexpr int RED = 2 * BW + 8;
+
+    S *tiles;
+    double *V, *Wm, *bnd, *dg, *eg;    // slot
+    double *Tm, *Mm, *Nm, *stage;      // LDS: T, V^T X, T^T V^T X (BW x BW each), SYR2K staging
+    double *red, *vec;                 // LDS: per-wave partial sums, small vectors
+    double *de;                        // LDS: bisection (aliases Tm.. stage)
+    int m, T, LD;
+    int tid, lane, wave;
+
+    __device__ S *tile_ptr(int I, int J) const { return tiles + tile_index(I, J, T) * TILE_ELEMS; }
+    __device__ double Mget(int r, int c) const {
+        return (double)tile_ptr(r >> 6, c >> 6)[mtile_off(r & 63, c & 63)];
+    }
+
+    // -------------------------------------------------------------- gather
+    __device__ void gather(const Item &it) {
+        const int n = it.n, j = it.j;
+        const double *A = it.src;
+        for (int J = 0; J < T; ++J)
+            for (int I = J; I < T; ++I) {
+                S *tp = tile_ptr(I, J);
+                for (int q = tid; q < TILE_ELEMS; q += NT) {
+                    const int sb = q >> 8, in = q & 255;
+                    const int r = ((sb & 3) << 4) + (in & 15), c = ((sb >> 2) << 4) + (in >> 4);
+                    const int row = I * TILE + r, col = J * TILE + c;
+                    double v = 0.0;
+                    if (row < m && col < m) {
+                        const int rs = row + ((j >= 0 && row >= j) ? 1 : 0);
+                        const int cs = col + ((j >= 0 && col >= j) ? 1 : 0);
+                        v = (rs >= cs) ? A[(int64_t)rs * n + cs] : A[(int64_t)cs * n + rs];
+                    }
+                    tp[q] = (S)v;
+                }
+            }
+        for (int q = tid; q < LD * BLD; q += NT) bnd[q] = 0.0;
+    }
+
+    // ------------------------------------------------------------ panel QR
+    // Block reduction of per-row products: lanes of every wave end with one
+    // column sum each (wave_transpose_sum); the column sums of all waves go to
+    // red[w * RED + off + c].
+    __device__ void to_red(double acc, int off) {
+        if ((lane & 1) == 0) red[wave * RED + off + (lane >> 1)] = acc;
+    }
+
+    // Left-looking Householder QR of P = A(r0:m, k0:k0+BW), r0 = k0 + BW:
+    // column c is brought up to date with the reflectors 0..c-1 of the panel
+    // (x = P(:,c) - V T^T V^T P(:,c)), then reflector c annihilates x below row
+    // r0 + c.  R goes to the band, v_c to V(:, c) (v_c(r0 + c) = 1), T to LDS.
+    __device__ void panel_qr(int k0) {
+        const int r0 = k0 + BW;
+        double *tv = vec;           // t = T^T V^T x (BW)
+        double *sc = vec + 64;      // scalars: [0] tau, [1] scal, [2] alpha
+        for (int c = 0; c <= BW; ++c) {
+            // ---- pass A: z = V(:,0:c)^T x_c, g = V(:,0:c-1)^T v_{c-1}
+            double accz = 0.0, accg = 0.0;
+            for (int r0i = r0; r0i < m; r0i += NT) {
+                asm volatile("" ::: "memory");
+                const int r = r0i + tid;
+                const bool live = r < m;
+                double vr[BW];
+#pragma unroll
+                for (int l = 0; l < BW; ++l) vr[l] = 0.0;
+                double x = 0.0, vp = 0.0;
+                if (live) {
+#pragma unroll
+                    for (int q = 0; q < BW / 8; ++q)
+                        if (q * 8 < c) {
+#pragma unroll
+                            for (int l = q * 8; l < q * 8 + 8; ++l) vr[l] = V[(int64_t)l * LD + r];
+                        }
+                    if (c < BW) x = Mget(r, k0 + c);
+                    if (c > 0) vp = V[(int64_t)(c - 1) * LD + r];
+                }
+                double wz[BW];
+#pragma unroll
+                for (int l = 0; l < BW; ++l) wz[l] = (l < c) ? vr[l] * x : 0.0;
+                accz += wave_transpose_sum<BW>(wz, lane);
+#pragma unroll
+                for (int l = 0; l < BW; ++l) wz[l] = (l + 1 < c) ? vr[l] * vp : 0.0;
+                accg += wave_transpose_sum<BW>(wz, lane);
+            }
+            to_red(accz, 0);
+            to_red(accg, BW);
+            __syncthreads();
+            if (wave == 0) {
+                double z = 0.0, g = 0.0;
+                if (lane < BW)
+                    for (int w = 0; w < NWAVE; ++w) { z += red[w * RED + lane]; g += red[w * RED + BW + lane]; }
+                // T(0:c-1, c-1) = -tau_{c-1} T(0:c-1, 0:c-1) g
+                if (c > 0) {
+                    if (lane < BW) tv[lane] = g;
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // LDS writes of this wave visible to it
+                    const double tau = Tm[(c - 1) * BW + (c - 1)];
+                    double s = 0.0;
+                    if (lane < c - 1)
+                        for (int l = lane; l < c - 1; ++l) s = fma(Tm[lane * BW + l], tv[l], s);
+                    if (lane < c - 1) Tm[lane * BW + (c - 1)] = -tau * s;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+                if (c < BW) {
+                    // t = T(0:c, 0:c)^T z
+                    if (lane < BW) tv[BW + lane] = z;
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+                    double s = 0.0;
+                    if (lane < c)
+                        for (int l = 0; l <= lane; ++l) s = fma(Tm[l * BW + lane], tv[BW + l], s);
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+                    if (lane < BW) tv[lane] = (lane < c) ? s : 0.0;
+                }
+            }
+            __syncthreads();
+            if (c == BW) break;
+            // ---- pass B: x = P(:,c) - V t; R entries above the diagonal to the band,
+            //      alpha = x(r0 + c), sigma = |x(r0+c+1:)|^2, x(r0+c+1:) kept in Wm(:, c)
+            double sig = 0.0;
+            for (int r0i = r0; r0i < m; r0i += NT) {
+                asm volatile("" ::: "memory");
+                const int r = r0i + tid;
+                if (r < m) {
+                    double s = Mget(r, k0 + c);
+#pragma unroll
+                    for (int q = 0; q < BW / 8; ++q)
+                        if (q * 8 < c) {
+#pragma unroll
+                            for (int l = q * 8; l < q * 8 + 8; ++l) s = fma(-V[(int64_t)l * LD + r], tv[l], s);
+                        }
+                    const int rr = r - r0;
+                    if (rr < c) bnd[(int64_t)(k0 + c) * BLD + (r - k0 - c)] = s;      // R(rr, c)
+                    else if (rr == c) sc[2] = s;
+                    else { sig = fma(s, s, sig); Wm[(int64_t)c * LD + r] = s; }
+                }
+            }
+            sig = wave_sum(sig);
+            if (lane == 0) red[wave * RED + 2 * BW] = sig;
+            __syncthreads();
+            if (tid == 0) {
+                double sg = 0.0;
+                for (int w = 0; w < NWAVE; ++w) sg += red[w * RED + 2 * BW];
+                double tau = 0.0, scal = 0.0;
+                if (r0 + c < m) {
+                    const double alpha = sc[2];
+                    double beta = alpha;
+                    if (sg != 0.0) {
+                        const double nrm = sqrt(fma(alpha, alpha, sg));
+                        beta = (alpha >= 0.0) ? -nrm : nrm;
+                        tau = (beta - alpha) / beta;
+                        scal = 1.0 / (alpha - beta);
+                    }
+                    bnd[(int64_t)(k0 + c) * BLD + BW] = beta;   // R(c, c) = A(r0 + c, k0 + c)
+                }
+                Tm[c * BW + c] = tau;
+                sc[0] = tau;
+                sc[1] = scal;
+            }
+            __syncthreads();
+            // ---- pass C: v_c
+            {
+                const double scal = sc[1];
+                for (int r = r0 + c + tid; r < m; r += NT)
+                    V[(int64_t)c * LD + r] = (r == r0 + c) ? 1.0 : Wm[(int64_t)c * LD + r] * scal;
+            }
+            __syncthreads();
+        }
+    }
+
+    // ---------------------------------------------------------------- SYMM
+    // Y = A22 V over tile rows/columns >= J1 in two passes of matrix-core
+    // products (f64 16x16x4, or f32 16x16x4 from an FP32 trailing matrix):
+    // column pass Y_J = sum_{I > J} A_IJ^T V_I (one wave per tile column),
+    // row pass Y_I += sum_{J1 <= J <= I} A_IJ V_J (one wave per tile row,
+    // diagonal tiles are stored whole).  Y goes to Wm (column l at l * LD).
+    //
+    // f64 16x16x4: operand a of lane l is A(l % 16, l / 16), operand b is
+    // B(l / 16, l % 16); result register g of lane l is D(l / 16 + 4 g, l % 16).
+    // f32 16x16x4: same operands; result register g is D(4 (l / 16) + g, l % 16).
+    __device__ void symm_tile(const S *tp, const double *vk, bool transposed, dbl4 (&acc)[4][2]) {
+        const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll 4
+        for (int kq = 0; kq < TILE; kq += 4) {
+            double bv[2];
+#pragma unroll
+            for (int jb = 0; jb < 2; ++jb) bv[jb] = vk[(int64_t)(jb * 16 + lr) * LD + kq + lk];
+#pragma unroll
+            for (int ib = 0; ib < 4; ++ib) {
+                // transposed: a = A(kq + lk, ib*16 + lr) (column pass); else a = A(ib*16 + lr, kq + lk)
+                const int off = transposed ? mtile_off(kq + lk, ib * 16 + lr) : mtile_off(ib * 16 + lr, kq + lk);
+                const double a = (double)tp[off];
+#pragma unroll
+                for (int jb = 0; jb < 2; ++jb) acc[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[jb], acc[ib][jb], 0, 0, 0);
+            }
+        }
+    }
+
+    __device__ void symm_tile32(const S *tp, const double *vk, bool transposed, flt4 (&acc)[4][2]) {
+        const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll 4
+        for (int kq = 0; kq < TILE; kq += 4) {
+            float bv[2];
+#pragma unroll
+            for (int jb = 0; jb < 2; ++jb) bv[jb] = (float)vk[(int64_t)(jb * 16 + lr) * LD + kq + lk];
+#pragma unroll
+            for (int ib = 0; ib < 4; ++ib) {
+                const int off = transposed ? mtile_off(kq + lk, ib * 16 + lr) : mtile_off(ib * 16 + lr, kq + lk);
+                const float a = (float)tp[off];
+#pragma unroll
+                for (int jb = 0; jb < 2; ++jb) acc[ib][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv[jb], acc[ib][jb], 0, 0, 0);
+            }
+        }
+    }
+
+    // Y block of tile row/column K (64 x BW) += or = the accumulators.
+    template <class ACC>
+    __device__ void store_y(int K, const ACC (&acc)[4][2], bool add) {
+        const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const int row = (sizeof(S) == 8) ? (lk + 4 * g) : (4 * lk + g);
+                    double *p = Wm + (int64_t)(jb * 16 + lr) * LD + K * TILE + ib * 16 + row;
+                    const double v = (double)acc[ib][jb][g];
+                    *p = add ? *p + v : v;
+                }
+    }
+
+    __device__ void symm(int J1) {
+        const int NJ = T - J1;
+        // column pass: tile column J1 + q has T - 1 - (J1 + q) tiles below the diagonal;
+        // columns dealt longest first in snake order
+        for (int q = 0; q < NJ; ++q) {
+            const int rnd = q / NWAVE, cc = q % NWAVE;
+            if (((rnd & 1) ? (NWAVE - 1 - cc) : cc) != wave) continue;
+            const int J = J1 + q;
+            if constexpr (sizeof(S) == 8) {
+                dbl4 acc[4][2];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) { acc[a][0] = dbl4{0, 0, 0, 0}; acc[a][1] = dbl4{0, 0, 0, 0}; }
+                for (int I = J + 1; I < T; ++I) symm_tile(tile_ptr(I, J), V + I * TILE, true, acc);
+                store_y(J, acc, false);
+            } else {
+                flt4 acc[4][2];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) { acc[a][0] = flt4{0, 0, 0, 0}; acc[a][1] = flt4{0, 0, 0, 0}; }
+                for (int I = J + 1; I < T; ++I) symm_tile32(tile_ptr(I, J), V + I * TILE, true, acc);
+                store_y(J, acc, false);
+            }
+        }
+        __syncthreads();
+        // row pass: tile row T - 1 - q has T - J1 - q tiles
+        for (int q = 0; q < NJ; ++q) {
+            const int rnd = q / NWAVE, cc = q % NWAVE;
+            if (((rnd & 1) ? (NWAVE - 1 - cc) : cc) != wave) continue;
+            const int I = T - 1 - q;
+            if constexpr (sizeof(S) == 8) {
+                dbl4 acc[4][2];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) { acc[a][0] = dbl4{0, 0, 0, 0}; acc[a][1] = dbl4{0, 0, 0, 0}; }
+                for (int J = J1; J <= I; ++J) symm_tile(tile_ptr(I, J), V + J * TILE, false, acc);
+                store_y(I, acc, true);
+            } else {
+                flt4 acc[4][2];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) { acc[a][0] = flt4{0, 0, 0, 0}; acc[a][1] = flt4{0, 0, 0, 0}; }
+                for (int J = J1; J <= I; ++J) symm_tile32(tile_ptr(I, J), V + J * TILE, false, acc);
+                store_y(I, acc, true);
+            }
+        }
+    }
+
+    // ------------------------------------------------------------ W from Y
+    // X = Y T (rows >= r0), M = V^T X (matrix cores, LDS atomics), N = T^T M,
+    // W = X - 1/2 V N; rows [J1*64, r0) of W are zero.
+    __device__ void make_w(int J1, int r0) {
+        for (int r = r0 + tid; r < LD; r += NT) {
+            double yr[BW];
+#pragma unroll
+            for (int l = 0; l < BW; ++l) yr[l] = Wm[(int64_t)l * LD + r];
+#pragma unroll
+            for (int l = BW - 1; l >= 0; --l) {
+                double s = 0.0;
+#pragma unroll
+                for (int l2 = 0; l2 <= l; ++l2) s = fma(yr[l2], Tm[l2 * BW + l], s);
+                yr[l] = s;
+            }
+#pragma unroll
+            for (int l = 0; l < BW; ++l) Wm[(int64_t)l * LD + r] = yr[l];
+        }
+        for (int q = tid; q < BW * BW; q += NT) Mm[q] = 0.0;
+        __syncthreads();
+        {
+            // M(i, j) = sum_r V(r, i) X(r, j): rows in chunks of 4 per MFMA, chunks dealt to waves
+            const int lr = lane & 15, lk = lane >> 4;
+            dbl4 acc[2][2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) { acc[a][0] = dbl4{0, 0, 0, 0}; acc[a][1] = dbl4{0, 0, 0, 0}; }
+            for (int rk = r0 + 4 * wave; rk < LD; rk += 4 * NWAVE) {
+                double av[2], bx[2];
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    av[q] = V[(int64_t)(q * 16 + lr) * LD + rk + lk];
+                    bx[q] = Wm[(int64_t)(q * 16 + lr) * LD + rk + lk];
+                }
+#pragma unroll
+                for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+                    for (int jb = 0; jb < 2; ++jb)
+                        acc[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ib], bx[jb], acc[ib][jb], 0, 0, 0);
+            }
+#pragma unroll
+            for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+                for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+                    for (int g = 0; g < 4; ++g)
+                        atomicAdd(&Mm[(ib * 16 + lk + 4 * g) * BW + jb * 16 + lr], acc[ib][jb][g]);
+        }
+        __syncthreads();
+        for (int q = tid; q < BW * BW; q += NT) {
+            const int i = q / BW, j = q % BW;
+            double s = 0.0;
+            for (int l = 0; l <= i; ++l) s = fma(Tm[l * BW + i], Mm[l * BW + j], s);
+            Nm[q] = s;
+        }
+        __syncthreads();
+        for (int r = J1 * TILE + tid; r < LD; r += NT) {
+            if (r < r0) {
+#pragma unroll
+                for (int l = 0; l < BW; ++l) Wm[(int64_t)l * LD + r] = 0.0;
+                continue;
+            }
+            double vr[BW], xr[BW];
+#pragma unroll
+            for (int l = 0; l < BW; ++l) { vr[l] = V[(int64_t)l * LD + r]; xr[l] = Wm[(int64_t)l * LD + r]; }
+#pragma unroll
+            for (int l = 0; l < BW; ++l) {
+                double s = 0.0;
+#pragma unroll
+                for (int l2 = 0; l2 < BW; ++l2) s = fma(vr[l2], Nm[l2 * BW + l], s);
+                Wm[(int64_t)l * LD + r] = fma(-0.5, s, xr[l]);
+            }
+        }
+    }
+
+    // ---------------------------------------------------------------- SYR2K
+    // C(I, J) -= V_I W_J^T + W_I V_J^T for tiles J >= J1, J-side rows staged in
+    // LDS per tile column (column k of the panel at vs[k*64 + row]).
+    __device__ void syr2k_tile(int I, const double *vs, const double *ws, int J) {
+        S *tp = tile_ptr(I, J);
+        const int lr = lane & 15, lk = lane >> 4;
+        const double *vI = V + I * TILE + lr, *wI = Wm + I * TILE + lr;
+#pragma unroll 1
+        for (int ip = 0; ip < 4; ip += 2) {
+            if constexpr (sizeof(S) == 8) {
+                dbl4 acc[4][2];  // [jb][ib - ip]
+#pragma unroll
+                for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+                    for (int ib = 0; ib < 2; ++ib) acc[jb][ib] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+                for (int kk = 0; kk < BW; kk += 4) {
+                    const int64_t col = (int64_t)(kk + lk) * LD;
+                    const int sc = (kk + lk) * TILE + lr;
+                    double aw[4], av[4], bv[2], bw[2];
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) { bv[q] = vI[col + (ip + q) * 16]; bw[q] = wI[col + (ip + q) * 16]; }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) { aw[q] = ws[sc + q * 16]; av[q] = vs[sc + q * 16]; }
+#pragma unroll
+                    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+                        for (int ib = 0; ib < 2; ++ib)
+                            acc[jb][ib] = __builtin_amdgcn_mfma_f64_16x16x4f64(aw[jb], bv[ib], acc[jb][ib], 0, 0, 0);
+#pragma unroll
+                    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+                        for (int ib = 0; ib < 2; ++ib)
+                            acc[jb][ib] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[jb], bw[ib], acc[jb][ib], 0, 0, 0);
+                }
+                // acc[jb][ib][g] = dC(row (ip+ib)*16 + lr, col jb*16 + lk + 4g): 64 lanes x one
+                // register cover 512 contiguous bytes of the tile
+#pragma unroll
+                for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+                    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+                        for (int g = 0; g < 4; ++g) {
+                            S *p = tp + mtile_off((ip + ib) * 16 + lr, jb * 16 + lk + 4 * g);
+                            __builtin_nontemporal_store(__builtin_nontemporal_load(p) - acc[jb][ib][g], p);
+                        }
+            } else {
+                flt4 acc[4][2];
+#pragma unroll
+                for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+                    for (int ib = 0; ib < 2; ++ib) acc[jb][ib] = flt4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+                for (int kk = 0; kk < BW; kk += 4) {
+                    const int64_t col = (int64_t)(kk + lk) * LD;
+                    const int sc = (kk + lk) * TILE + lr;
+                    float aw[4], av[4], bv[2], bw[2];
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        bv[q] = (float)vI[col + (ip + q) * 16];
+                        bw[q] = (float)wI[col + (ip + q) * 16];
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) { aw[q] = (float)ws[sc + q * 16]; av[q] = (float)vs[sc + q * 16]; }
+#pragma unroll
+                    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+                        for (int ib = 0; ib < 2; ++ib)
+                            acc[jb][ib] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw[jb], bv[ib], acc[jb][ib], 0, 0, 0);
+#pragma unroll
+                    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+                        for (int ib = 0; ib < 2; ++ib)
+                            acc[jb][ib] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[jb], bw[ib], acc[jb][ib], 0, 0, 0);
+                }
+                // acc[jb][ib][g] = dC(row (ip+ib)*16 + lr, col jb*16 + 4 lk + g)
+#pragma unroll
+                for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+                    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+                        for (int g = 0; g < 4; ++g) {
+                            S *p = tp + mtile_off((ip + ib) * 16 + lr, jb * 16 + 4 * lk + g);
+                            __builtin_nontemporal_store(__builtin_nontemporal_load(p) - acc[jb][ib][g], p);
+                        }
+            }
+        }
+    }
+
+    __device__ void syr2k(int J1) {
+        double *vs = stage, *ws = stage + BW * TILE;
+        for (int J = J1; J < T; ++J) {
+            for (int q = tid; q < BW * TILE; q += NT) {
+                const int kc = q / TILE, r = q % TILE;
+                vs[q] = V[(int64_t)kc * LD + J * TILE + r];
+                ws[q] = Wm[(int64_t)kc * LD + J * TILE + r];
+            }
+            __syncthreads();
+            for (int I = J + wave; I < T; I += NWAVE) syr2k_tile(I, vs, ws, J);
+            __syncthreads();
+        }
+    }
+
+    // --------------------------------------------------------------- stage 1
+    __device__ void reduce_to_band() {
+        for (int k0 = 0; k0 < m; k0 += BW) {
+            const int kb = min(BW, m - k0);
+            // diagonal block A(k0:k0+kb, k0:k0+kb) is final: lower triangle to the band
+            for (int q = tid; q < BW * BW; q += NT) {
+                const int i = q % BW, j = q / BW;
+                if (j <= i && i < kb) bnd[(int64_t)(k0 + j) * BLD + (i - j)] = Mget(k0 + i, k0 + j);
+            }
+            const int r0 = k0 + BW;
+            if (r0 >= m) break;
+            {   // clear V and W from the first tile row the update can touch
+                const int rz = (k0 / TILE) * TILE, len = LD - rz;
+                for (int q = tid; q < BW * len; q += NT) {
+                    const int l = q / len, r = rz + q % len;
+                    V[(int64_t)l * LD + r] = 0.0;
+                    Wm[(int64_t)l * LD + r] = 0.0;
+                }
+                for (int q = tid; q < BW * BW; q += NT) Tm[q] = 0.0;
+            }
+            __syncthreads();
+            panel_qr(k0);
+            const int J1 = r0 / TILE;
+            symm(J1);
+            __syncthreads();
+            make_w(J1, r0);
+            __syncthreads();
+            syr2k(J1);
+            __syncthreads();
+        }
+    }
+
+    // --------------------------------------------------------------- stage 2
+    // Bulge chasing, one sweep per wave: wave w takes sweeps w, w + NWAVE, ...
+    // Step t of sweep s acts on rows s + 1 + t BW .. s + (t + 1) BW, which were
+    // last written by sweep s - 1 in its steps t and t + 1; step t + 2 of sweep
+    // s - 1 touches only rows below that, so sweep s runs two steps behind
+    // sweep s - 1.  Progress counters in LDS (sweep * 4096 + steps done, 4095
+    // when the sweep is complete) order the waves; band writes are released
+    // and acquired at workgroup scope around them.
+    // Lane l holds row i = l % 32 of a BW x BW block and its columns
+    // 16 h .. 16 h + 15, h = l / 32.
+    __device__ double colsum32(double (&p)[16]) {
+        // sum of p[q] over the 32 lanes of this half; returns the sum of column
+        // 8 b4 + 4 b3 + 2 b2 + b1 (b_k = bit k of the lane) of this half
+        halve_step<16, 16>(p, lane);
+        halve_step<8, 8>(p, lane);
+        halve_step<4, 4>(p, lane);
+        halve_step<2, 2>(p, lane);
+        return p[0] + __shfl_xor(p[0], 1);
+    }
+
+    __device__ void band_to_tridiagonal(double *scratch) {
+        int *prog = reinterpret_cast<int *>(scratch + NWAVE * 4 * BW);
+        if (tid < NWAVE) prog[tid] = (tid - NWAVE) * 4096 + 4095;
+        __syncthreads();
+        const int i = lane & 31, hh = lane >> 5;
+        double *vp = scratch + wave * 4 * BW, *vc = vp + BW, *wv = vp + 2 * BW, *cs = vp + 3 * BW;
+        const int csel = (((lane >> 4) & 1) << 3) | (((lane >> 3) & 1) << 2) | (((lane >> 2) & 1) << 1) | ((lane >> 1) & 1);
+        const int pw = (wave + NWAVE - 1) % NWAVE;
+        for (int s = wave; s + 2 < m; s += NWAVE) {
+            double taup = 0.0;
+            int plo = 0, pL = 0;
+            for (int t = 0;; ++t) {
+                const int lo = s + 1 + t * BW;
+                if (lo > m - 1) break;
+                const int L = min(BW, m - lo);
+                if (s > 0) {
+                    const int need = (s - 1) * 4096 + min(t + 2, 4095);
+                    while (__atomic_load_n(&prog[pw], __ATOMIC_RELAXED) < need) __builtin_amdgcn_s_sleep(1);
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                }
+                // all loads of the step at once: the block below the previous
+                // diagonal block (or column s) and the diagonal block
+                double bk[16], dk[16];
+                double x = 0.0;
+                if (t == 0) {
+                    x = (i < L) ? bnd[(int64_t)s * BLD + (lo + i - s)] : 0.0;
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        const int c = hh * 16 + q;
+                        bk[q] = (i < L && c < pL) ? bnd[(int64_t)(plo + c) * BLD + (lo + i - plo - c)] : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int c = hh * 16 + q;
+                    double d = 0.0;
+                    if (L >= 2 && i < L && c < L)
+                        d = (c <= i) ? bnd[(int64_t)(lo + c) * BLD + (i - c)] : bnd[(int64_t)(lo + i) * BLD + (c - i)];
+                    dk[q] = d;
+                }
+                // publish the previous step: its stores complete together with these loads
+                if (t > 0) {
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                    if (lane == 0) __atomic_store_n(&prog[wave], s * 4096 + t, __ATOMIC_RELAXED);
+                }
+                if (t > 0) {
+                    double u = 0.0;
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) u = fma(bk[q], vp[hh * 16 + q], u);
+                    u += __shfl_xor(u, 32);
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) bk[q] = fma(-taup * u, vp[hh * 16 + q], bk[q]);
+                    x = __shfl(bk[0], i);  // column 0 of the block: lane i of half 0
+                }
+                double tau = 0.0, beta = 0.0, v = 0.0;
+                if (L >= 2) {
+                    const double alpha = __shfl(x, 0);
+                    const double sg = wave_sum((hh == 0 && i >= 1 && i < L) ? x * x : 0.0);
+                    double scal = 0.0;
+                    beta = alpha;
+                    if (sg != 0.0) {
+                        const double nrm = sqrt(fma(alpha, alpha, sg));
+                        beta = (alpha >= 0.0) ? -nrm : nrm;
+                        tau = (beta - alpha) / beta;
+                        scal = 1.0 / (alpha - beta);
+                    }
+                    v = (i == 0) ? 1.0 : ((i < L) ? x * scal : 0.0);
+                } else {
+                    beta = __shfl(x, 0);
+                    v = (i == 0) ? 1.0 : 0.0;
+                }
+                if (hh == 0) vc[i] = v;
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                if (t == 0) {
+                    if (hh == 0 && i < L) bnd[(int64_t)s * BLD + (lo + i - s)] = (i == 0) ? beta : 0.0;
+                } else {
+                    // left-apply to the columns 1.. of the block; column 0 becomes beta e0
+                    double p[16];
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) p[q] = v * bk[q];
+                    const double sum = colsum32(p);
+                    if ((lane & 1) == 0) cs[hh * 16 + csel] = sum;
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        const int c = hh * 16 + q;
+                        bk[q] = (c == 0) ? ((i == 0) ? beta : 0.0) : fma(-tau * v, cs[c], bk[q]);
+                        if (i < L && c < pL) bnd[(int64_t)(plo + c) * BLD + (lo + i - plo - c)] = bk[q];
+                    }
+                }
+                if (L < 2) break;
+                // two-sided update of the diagonal block D = A(lo:lo+L, lo:lo+L)
+                double pr = 0.0;
+#pragma unroll
+                for (int q = 0; q < 16; ++q) pr = fma(dk[q], vc[hh * 16 + q], pr);
+                pr += __shfl_xor(pr, 32);
+                const double w0 = tau * pr;
+                const double kap = 0.5 * tau * wave_sum((hh == 0) ? v * w0 : 0.0);
+                const double w = fma(-kap, v, w0);
+                if (hh == 0) wv[i] = w;
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int c = hh * 16 + q;
+                    dk[q] -= fma(v, wv[c], w * vc[c]);
+                    if (i < L && c <= i) bnd[(int64_t)(lo + c) * BLD + (i - c)] = dk[q];
+                }
+                // this reflector is applied from the right in the next step
+                if (hh == 0) vp[i] = v;
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                taup = tau;
+                plo = lo;
+                pL = L;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            if (lane == 0) __atomic_store_n(&prog[wave], s * 4096 + 4095, __ATOMIC_RELAXED);
+        }
+        __syncthreads();
+        for (int r = tid; r < m; r += NT) {
+            dg[r] = bnd[(int64_t)r * BLD];
+            if (r + 1 < m) eg[r] = bnd[(int64_t)r * BLD + 1];
+        }
+        __syncthreads();
+    }
+
+    __device__ void bisect(double *out) { bisect_tridiagonal<NT, 4>(dg, eg, m, out, de, red, tid, lane, wave); }
+};
+
+template <class S>
+__host__ __device__ inline int64_t slot_bytes_band(int LDmax) {
+    const int64_t T = LDmax / TILE;
+    const int64_t tiles = T * (T + 1) / 2 * TILE_ELEMS * (int64_t)sizeof(S);
+    const int64_t panel = 2 * (int64_t)BW * LDmax * 8;
+    const int64_t band = (int64_t)LDmax * BLD * 8;
+    const int64_t de = 2 * (int64_t)LDmax * 8;
+    return ((tiles + 255) / 256) * 256 + panel + band + de;
+}
+
+template <int NT>
+__host__ __device__ inline int64_t lds_bytes_band(int LDmax) {
+    const int64_t shared = 3 * BW * BW + 2 * BW * TILE;  // T, M, N, SYR2K staging; the bisection reuses it
+    const int64_t big = (shared > 2 * (int64_t)LDmax) ? shared : 2 * (int64_t)LDmax;
+    return (big + (NT / 64) * (2 * BW + 8) + 160) * 8 + 64;
+}
+
+template <class S, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void band_bisect_kernel(TriArgs args) {
+    extern __shared__ double lds[];
+    __shared__ int s_item;
+    Band<S, NT> t;
+    t.tid = threadIdx.x;
+    t.lane = threadIdx.x & 63;
+    t.wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int LDmax = args.LDmax;
+    const int64_t shared = 3 * BW * BW + 2 * BW * TILE;
+    const int64_t big = (shared > 2 * (int64_t)LDmax) ? shared : 2 * (int64_t)LDmax;
+    t.Tm = lds;
+    t.Mm = lds + BW * BW;
+    t.Nm = lds + 2 * BW * BW;
+    t.stage = lds + 3 * BW * BW;
+    t.de = lds;
+    t.red = lds + big;
+    t.vec = t.red + (NT / 64) * (2 * BW + 8);
+    char *slot = args.work + (int64_t)blockIdx.x * args.slot_bytes;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(args.counter, 1);
+        __syncthreads();
+        const int64_t it_idx = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();
+        if (it_idx >= args.n_items) break;
+        const Item it = args.items[it_idx];
+        if (args.flags[it.b] & 1) {
+            for (int i = threadIdx.x; i < it.m; i += NT) it.out[i] = __builtin_nan("");
+            continue;
+        }
+        t.m = it.m;
+        t.T = (it.m + TILE - 1) / TILE;
+        t.LD = t.T * TILE;
+        t.tiles = reinterpret_cast<S *>(slot);
+        const int64_t T = t.T;
+        const int64_t tile_bytes = ((T * (T + 1) / 2 * TILE_ELEMS * (int64_t)sizeof(S) + 255) / 256) * 256;
+        t.V = reinterpret_cast<double *>(slot + tile_bytes);
+        t.Wm = t.V + (int64_t)BW * t.LD;
+        t.bnd = t.Wm + (int64_t)BW * t.LD;
+        t.dg = t.bnd + (int64_t)BLD * t.LD;
+        t.eg = t.dg + t.LD;
+        t.gather(it);
+        __syncthreads();
+        t.reduce_to_band();
+        __syncthreads();
+        t.band_to_tridiagonal(t.Tm);
+        t.bisect(it.out);
+        __syncthreads();
+    }
+}
+
+}  // namespace eeid
