@@ -213,15 +213,15 @@ struct Band {
     }
 
     // ---------------------------------------------------------------- SYMM
-    // Y = A22 V over tile rows/columns >= J1 in two passes of matrix-core
-    // products (f64 16x16x4, or f32 16x16x4 from an FP32 trailing matrix):
+    // Y = A22 V over tile rows/columns >= J1 in two passes of f64 16x16x4
+    // matrix-core products (an FP32 trailing matrix is widened on load, so Y
+    // accumulates in FP64 in both forms; only the update is FP32 arithmetic):
     // column pass Y_J = sum_{I > J} A_IJ^T V_I (one wave per tile column),
     // row pass Y_I += sum_{J1 <= J <= I} A_IJ V_J (one wave per tile row,
     // diagonal tiles are stored whole).  Y goes to Wm (column l at l * LD).
     //
     // f64 16x16x4: operand a of lane l is A(l % 16, l / 16), operand b is
     // B(l / 16, l % 16); result register g of lane l is D(l / 16 + 4 g, l % 16).
-    // f32 16x16x4: same operands; result register g is D(4 (l / 16) + g, l % 16).
     __device__ void symm_tile(const S *tp, const double *vk, bool transposed, dbl4 (&acc)[4][2]) {
         const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll 4
@@ -240,26 +240,8 @@ struct Band {
         }
     }
 
-    __device__ void symm_tile32(const S *tp, const double *vk, bool transposed, flt4 (&acc)[4][2]) {
-        const int lr = lane & 15, lk = lane >> 4;
-#pragma unroll 4
-        for (int kq = 0; kq < TILE; kq += 4) {
-            float bv[2];
-#pragma unroll
-            for (int jb = 0; jb < 2; ++jb) bv[jb] = (float)vk[(int64_t)(jb * 16 + lr) * LD + kq + lk];
-#pragma unroll
-            for (int ib = 0; ib < 4; ++ib) {
-                const int off = transposed ? mtile_off(kq + lk, ib * 16 + lr) : mtile_off(ib * 16 + lr, kq + lk);
-                const float a = (float)tp[off];
-#pragma unroll
-                for (int jb = 0; jb < 2; ++jb) acc[ib][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv[jb], acc[ib][jb], 0, 0, 0);
-            }
-        }
-    }
-
     // Y block of tile row/column K (64 x BW) += or = the accumulators.
-    template <class ACC>
-    __device__ void store_y(int K, const ACC (&acc)[4][2], bool add) {
+    __device__ void store_y(int K, const dbl4 (&acc)[4][2], bool add) {
         const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll
         for (int ib = 0; ib < 4; ++ib)
@@ -267,7 +249,7 @@ struct Band {
             for (int jb = 0; jb < 2; ++jb)
 #pragma unroll
                 for (int g = 0; g < 4; ++g) {
-                    const int row = (sizeof(S) == 8) ? (lk + 4 * g) : (4 * lk + g);
+                    const int row = lk + 4 * g;
                     double *p = Wm + (int64_t)(jb * 16 + lr) * LD + K * TILE + ib * 16 + row;
                     const double v = (double)acc[ib][jb][g];
                     *p = add ? *p + v : v;
@@ -282,19 +264,11 @@ struct Band {
             const int rnd = q / NWAVE, cc = q % NWAVE;
             if (((rnd & 1) ? (NWAVE - 1 - cc) : cc) != wave) continue;
             const int J = J1 + q;
-            if constexpr (sizeof(S) == 8) {
-                dbl4 acc[4][2];
+            dbl4 acc[4][2];
 #pragma unroll
-                for (int a = 0; a < 4; ++a) { acc[a][0] = dbl4{0, 0, 0, 0}; acc[a][1] = dbl4{0, 0, 0, 0}; }
-                for (int I = J + 1; I < T; ++I) symm_tile(tile_ptr(I, J), V + I * TILE, true, acc);
-                store_y(J, acc, false);
-            } else {
-                flt4 acc[4][2];
-#pragma unroll
-                for (int a = 0; a < 4; ++a) { acc[a][0] = flt4{0, 0, 0, 0}; acc[a][1] = flt4{0, 0, 0, 0}; }
-                for (int I = J + 1; I < T; ++I) symm_tile32(tile_ptr(I, J), V + I * TILE, true, acc);
-                store_y(J, acc, false);
-            }
+            for (int a = 0; a < 4; ++a) { acc[a][0] = dbl4{0, 0, 0, 0}; acc[a][1] = dbl4{0, 0, 0, 0}; }
+            for (int I = J + 1; I < T; ++I) symm_tile(tile_ptr(I, J), V + I * TILE, true, acc);
+            store_y(J, acc, false);
         }
         __syncthreads();
         // row pass: tile row T - 1 - q has T - J1 - q tiles
@@ -302,19 +276,11 @@ struct Band {
             const int rnd = q / NWAVE, cc = q % NWAVE;
             if (((rnd & 1) ? (NWAVE - 1 - cc) : cc) != wave) continue;
             const int I = T - 1 - q;
-            if constexpr (sizeof(S) == 8) {
-                dbl4 acc[4][2];
+            dbl4 acc[4][2];
 #pragma unroll
-                for (int a = 0; a < 4; ++a) { acc[a][0] = dbl4{0, 0, 0, 0}; acc[a][1] = dbl4{0, 0, 0, 0}; }
-                for (int J = J1; J <= I; ++J) symm_tile(tile_ptr(I, J), V + J * TILE, false, acc);
-                store_y(I, acc, true);
-            } else {
-                flt4 acc[4][2];
-#pragma unroll
-                for (int a = 0; a < 4; ++a) { acc[a][0] = flt4{0, 0, 0, 0}; acc[a][1] = flt4{0, 0, 0, 0}; }
-                for (int J = J1; J <= I; ++J) symm_tile32(tile_ptr(I, J), V + J * TILE, false, acc);
-                store_y(I, acc, true);
-            }
+            for (int a = 0; a < 4; ++a) { acc[a][0] = dbl4{0, 0, 0, 0}; acc[a][1] = dbl4{0, 0, 0, 0}; }
+            for (int J = J1; J <= I; ++J) symm_tile(tile_ptr(I, J), V + J * TILE, false, acc);
+            store_y(I, acc, true);
         }
     }
 
