@@ -49,7 +49,8 @@ def kernel_sources_hash() -> str:
 
 
 # compiled configurations of the eigenvalue kernel (eeid.VARIANTS): panel width NB, threads per block NT
-VARIANT_SHAPE = {"nb32_nt512": (32, 512), "nb32_nt256x2": (32, 256), "nb16_nt512": (16, 512), "band32_nt512": (32, 512)}
+VARIANT_SHAPE = {"nb32_nt512": (32, 512), "nb32_nt256x2": (32, 256), "nb16_nt512": (16, 512), "band32_nt512": (32, 512),
+                 "band32_nt256x2": (32, 256)}
 
 
 def kernel_name(form: str, variant: str) -> str:

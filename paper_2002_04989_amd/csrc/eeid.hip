@@ -40,8 +40,9 @@ typedef std::function<hipError_t(hipStream_t)> Enqueue;
 // Compiled configurations of the real eigenvalue kernel (the complex kernel
 // has one): one-stage reduction with panel width NB and threads per
 // workgroup, or the two-stage (dense -> band -> tridiagonal) reduction.
-constexpr int N_REAL_VARIANTS = 4;
-const char *const VARIANT_NAME[N_REAL_VARIANTS] = {"nb32_nt512", "nb32_nt256x2", "nb16_nt512", "band32_nt512"};
+constexpr int N_REAL_VARIANTS = 5;
+const char *const VARIANT_NAME[N_REAL_VARIANTS] = {"nb32_nt512", "nb32_nt256x2", "nb16_nt512", "band32_nt512",
+                                                   "band32_nt256x2"};
 
 }  // namespace
 
@@ -202,6 +203,7 @@ KernelChoice choose_kernel(eeid_dtype_t t, eeid_prec_t p, int variant, int LDmax
         case 1: return d ? real_kernel<double, 32, 256>(LDmax) : real_kernel<float, 32, 256>(LDmax);
         case 2: return d ? real_kernel<double, 16, 512>(LDmax) : real_kernel<float, 16, 512>(LDmax);
         case 3: return d ? band_kernel<double, 512>(LDmax) : band_kernel<float, 512>(LDmax);
+        case 4: return d ? band_kernel<double, 256>(LDmax) : band_kernel<float, 256>(LDmax);
         default: return d ? real_kernel<double, 32, 512>(LDmax) : real_kernel<float, 32, 512>(LDmax);
     }
 }

@@ -29,7 +29,10 @@
 // (r, c) at ((c / 16) * 4 + r / 16) * 256 + (c % 16) * 16 + r % 16.  Each
 // matrix-core operand then loads as 512 contiguous bytes (FP64).
 // Band storage: column c holds A(c + d, c), d in [0, 2 BW), at bnd[c * BLD + d]
-// (the chase leaves fill up to d = 2 BW - 1 during a step).
+// (the chase leaves fill up to d = 2 BW - 1 during a step), for LD + BW
+// columns; entries outside the matrix stay zero.  The trailing
+// matrix is streamed with non-temporal accesses so that it does not evict the
+// band, V and W of the problems in the chase from L2.
 #pragma once
 #include "eeid_tridiag.hpp"
 
@@ -77,10 +80,10 @@ struct Band {
                         const int cs = col + ((j >= 0 && col >= j) ? 1 : 0);
                         v = (rs >= cs) ? A[(int64_t)rs * n + cs] : A[(int64_t)cs * n + rs];
                     }
-                    tp[q] = (S)v;
+                    __builtin_nontemporal_store((S)v, tp + q);
                 }
             }
-        for (int q = tid; q < LD * BLD; q += NT) bnd[q] = 0.0;
+        for (int q = tid; q < (LD + BW) * BLD; q += NT) bnd[q] = 0.0;
     }
 
     // ------------------------------------------------------------ panel QR
@@ -138,22 +141,22 @@ struct Band {
                 // T(0:c-1, c-1) = -tau_{c-1} T(0:c-1, 0:c-1) g
                 if (c > 0) {
                     if (lane < BW) tv[lane] = g;
-                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // LDS writes of this wave visible to it
+                    __builtin_amdgcn_wave_barrier();  // LDS accesses of one wave complete in order
                     const double tau = Tm[(c - 1) * BW + (c - 1)];
                     double s = 0.0;
                     if (lane < c - 1)
                         for (int l = lane; l < c - 1; ++l) s = fma(Tm[lane * BW + l], tv[l], s);
                     if (lane < c - 1) Tm[lane * BW + (c - 1)] = -tau * s;
                 }
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+                __builtin_amdgcn_wave_barrier();
                 if (c < BW) {
                     // t = T(0:c, 0:c)^T z
                     if (lane < BW) tv[BW + lane] = z;
-                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+                    __builtin_amdgcn_wave_barrier();
                     double s = 0.0;
                     if (lane < c)
                         for (int l = 0; l <= lane; ++l) s = fma(Tm[l * BW + lane], tv[BW + l], s);
-                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+                    __builtin_amdgcn_wave_barrier();
                     if (lane < BW) tv[lane] = (lane < c) ? s : 0.0;
                 }
             }
@@ -219,39 +222,106 @@ struct Band {
     // column pass Y_J = sum_{I > J} A_IJ^T V_I (one wave per tile column),
     // row pass Y_I += sum_{J1 <= J <= I} A_IJ V_J (one wave per tile row,
     // diagonal tiles are stored whole).  Y goes to Wm (column l at l * LD).
+    // The operands of 8 K-steps are loaded while those of the previous 8 feed
+    // the matrix cores.
     //
     // f64 16x16x4: operand a of lane l is A(l % 16, l / 16), operand b is
     // B(l / 16, l % 16); result register g of lane l is D(l / 16 + 4 g, l % 16).
-    __device__ void symm_tile(const S *tp, const double *vk, bool transposed, dbl4 (&acc)[4][2]) {
+    typedef double dpair __attribute__((ext_vector_type(2)));
+    typedef S spair __attribute__((ext_vector_type(2)));
+
+    // Column pass, tile (I, J): Y_J += A_IJ^T V_I.  K runs down the tile rows in
+    // pairs: lane l loads rows kq + 2 (l / 16) and + 1 of column cb*16 + l % 16
+    // (one 16- or 8-byte load) and the matching two rows of V_I, and feeds two
+    // MFMAs.  acc[cb][jb] holds Y_J(cb*16 + i, jb*16 + j).
+    struct ColOps { spair a[4]; dpair b[2]; };
+    __device__ __forceinline__ void col_load(ColOps &o, const S *tp, const double *vI, int kq) const {
         const int lr = lane & 15, lk = lane >> 4;
-#pragma unroll 4
-        for (int kq = 0; kq < TILE; kq += 4) {
-            double bv[2];
 #pragma unroll
-            for (int jb = 0; jb < 2; ++jb) bv[jb] = vk[(int64_t)(jb * 16 + lr) * LD + kq + lk];
+        for (int cb = 0; cb < 4; ++cb)
+            o.a[cb] = __builtin_nontemporal_load(reinterpret_cast<const spair *>(tp + mtile_off(kq + 2 * lk, cb * 16 + lr)));
 #pragma unroll
-            for (int ib = 0; ib < 4; ++ib) {
-                // transposed: a = A(kq + lk, ib*16 + lr) (column pass); else a = A(ib*16 + lr, kq + lk)
-                const int off = transposed ? mtile_off(kq + lk, ib * 16 + lr) : mtile_off(ib * 16 + lr, kq + lk);
-                const double a = (double)tp[off];
+        for (int jb = 0; jb < 2; ++jb)
+            o.b[jb] = *reinterpret_cast<const dpair *>(vI + (int64_t)(jb * 16 + lr) * LD + kq + 2 * lk);
+    }
+    __device__ __forceinline__ void col_mfma(const ColOps &o, dbl4 (&acc)[4][2]) const {
 #pragma unroll
-                for (int jb = 0; jb < 2; ++jb) acc[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[jb], acc[ib][jb], 0, 0, 0);
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int jb = 0; jb < 2; ++jb) {
+                acc[cb][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)o.a[cb].x, o.b[jb].x, acc[cb][jb], 0, 0, 0);
+                acc[cb][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)o.a[cb].y, o.b[jb].y, acc[cb][jb], 0, 0, 0);
             }
+    }
+    __device__ void symm_col_tile(const S *tp, const double *vI, dbl4 (&acc)[4][2]) const {
+        ColOps o0, o1;
+        col_load(o0, tp, vI, 0);
+#pragma unroll 1
+        for (int kq = 0; kq < TILE; kq += 16) {
+            col_load(o1, tp, vI, kq + 8);
+            __builtin_amdgcn_sched_barrier(0);
+            col_mfma(o0, acc);
+            if (kq + 16 < TILE) col_load(o0, tp, vI, kq + 16);
+            __builtin_amdgcn_sched_barrier(0);
+            col_mfma(o1, acc);
         }
     }
 
-    // Y block of tile row/column K (64 x BW) += or = the accumulators.
-    __device__ void store_y(int K, const dbl4 (&acc)[4][2], bool add) {
+    // Row pass, tile (I, J): Y_I += A_IJ V_J.  Lane l loads rows h*32 + 2 (l % 16)
+    // and + 1 of column kq + l / 16 (consecutive in a sub-block); the even rows
+    // feed one MFMA and the odd rows another.  acc[2h + p][jb] holds
+    // Y_I(h*32 + 2 i + p, jb*16 + j).
+    struct RowOps { spair a[2][2]; double b[2][2]; };   // [kk][h], [kk][jb]
+    __device__ __forceinline__ void row_load(RowOps &o, const S *tp, const double *vJ, int kq) const {
         const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll
-        for (int ib = 0; ib < 4; ++ib)
+        for (int kk = 0; kk < 2; ++kk) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                o.a[kk][h] = __builtin_nontemporal_load(reinterpret_cast<const spair *>(tp + mtile_off(h * 32 + 2 * lr, kq + 4 * kk + lk)));
+#pragma unroll
+            for (int jb = 0; jb < 2; ++jb) o.b[kk][jb] = vJ[(int64_t)(jb * 16 + lr) * LD + kq + 4 * kk + lk];
+        }
+    }
+    __device__ __forceinline__ void row_mfma(const RowOps &o, dbl4 (&acc)[4][2]) const {
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int jb = 0; jb < 2; ++jb) {
+                    acc[2 * h][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)o.a[kk][h].x, o.b[kk][jb], acc[2 * h][jb], 0, 0, 0);
+                    acc[2 * h + 1][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)o.a[kk][h].y, o.b[kk][jb], acc[2 * h + 1][jb], 0, 0, 0);
+                }
+    }
+    __device__ void symm_row_tile(const S *tp, const double *vJ, dbl4 (&acc)[4][2]) const {
+        RowOps o0, o1;
+        row_load(o0, tp, vJ, 0);
+#pragma unroll 1
+        for (int kq = 0; kq < TILE; kq += 16) {
+            row_load(o1, tp, vJ, kq + 8);
+            __builtin_amdgcn_sched_barrier(0);
+            row_mfma(o0, acc);
+            if (kq + 16 < TILE) row_load(o0, tp, vJ, kq + 16);
+            __builtin_amdgcn_sched_barrier(0);
+            row_mfma(o1, acc);
+        }
+    }
+
+    // Y block of tile row/column K (64 x BW) from the accumulators: result
+    // register g of lane l is D(l / 16 + 4 g, l % 16) of block acc[x][jb], which
+    // is Y row `rowof(x, l / 16 + 4 g)` of the block, column jb*16 + l % 16.
+    template <class RowOf>
+    __device__ void store_y(int K, const dbl4 (&acc)[4][2], bool add, RowOf rowof) {
+        const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
 #pragma unroll
             for (int jb = 0; jb < 2; ++jb)
 #pragma unroll
                 for (int g = 0; g < 4; ++g) {
-                    const int row = lk + 4 * g;
-                    double *p = Wm + (int64_t)(jb * 16 + lr) * LD + K * TILE + ib * 16 + row;
-                    const double v = (double)acc[ib][jb][g];
+                    double *p = Wm + (int64_t)(jb * 16 + lr) * LD + K * TILE + rowof(x, lk + 4 * g);
+                    const double v = acc[x][jb][g];
                     *p = add ? *p + v : v;
                 }
     }
@@ -267,8 +337,8 @@ struct Band {
             dbl4 acc[4][2];
 #pragma unroll
             for (int a = 0; a < 4; ++a) { acc[a][0] = dbl4{0, 0, 0, 0}; acc[a][1] = dbl4{0, 0, 0, 0}; }
-            for (int I = J + 1; I < T; ++I) symm_tile(tile_ptr(I, J), V + I * TILE, true, acc);
-            store_y(J, acc, false);
+            for (int I = J + 1; I < T; ++I) symm_col_tile(tile_ptr(I, J), V + I * TILE, acc);
+            store_y(J, acc, false, [](int x, int i) { return x * 16 + i; });
         }
         __syncthreads();
         // row pass: tile row T - 1 - q has T - J1 - q tiles
@@ -279,8 +349,8 @@ struct Band {
             dbl4 acc[4][2];
 #pragma unroll
             for (int a = 0; a < 4; ++a) { acc[a][0] = dbl4{0, 0, 0, 0}; acc[a][1] = dbl4{0, 0, 0, 0}; }
-            for (int J = J1; J <= I; ++J) symm_tile(tile_ptr(I, J), V + J * TILE, false, acc);
-            store_y(I, acc, true);
+            for (int J = J1; J <= I; ++J) symm_row_tile(tile_ptr(I, J), V + J * TILE, acc);
+            store_y(I, acc, true, [](int x, int i) { return (x >> 1) * 32 + 2 * i + (x & 1); });
         }
     }
 
@@ -394,16 +464,23 @@ struct Band {
                             acc[jb][ib] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[jb], bw[ib], acc[jb][ib], 0, 0, 0);
                 }
                 // acc[jb][ib][g] = dC(row (ip+ib)*16 + lr, col jb*16 + lk + 4g): 64 lanes x one
-                // register cover 512 contiguous bytes of the tile
+                // register cover 512 contiguous bytes of the tile.  All loads of a
+                // 16-row block are issued before its stores.
 #pragma unroll
-                for (int ib = 0; ib < 2; ++ib)
+                for (int ib = 0; ib < 2; ++ib) {
+                    S c[4][4];
 #pragma unroll
                     for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
-                        for (int g = 0; g < 4; ++g) {
-                            S *p = tp + mtile_off((ip + ib) * 16 + lr, jb * 16 + lk + 4 * g);
-                            __builtin_nontemporal_store(__builtin_nontemporal_load(p) - acc[jb][ib][g], p);
-                        }
+                        for (int g = 0; g < 4; ++g)
+                            c[jb][g] = __builtin_nontemporal_load(tp + mtile_off((ip + ib) * 16 + lr, jb * 16 + lk + 4 * g));
+#pragma unroll
+                    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+                        for (int g = 0; g < 4; ++g)
+                            __builtin_nontemporal_store(c[jb][g] - acc[jb][ib][g],
+                                                        tp + mtile_off((ip + ib) * 16 + lr, jb * 16 + lk + 4 * g));
+                }
             } else {
                 flt4 acc[4][2];
 #pragma unroll
@@ -435,14 +512,20 @@ struct Band {
                 }
                 // acc[jb][ib][g] = dC(row (ip+ib)*16 + lr, col jb*16 + 4 lk + g)
 #pragma unroll
-                for (int ib = 0; ib < 2; ++ib)
+                for (int ib = 0; ib < 2; ++ib) {
+                    S c[4][4];
 #pragma unroll
                     for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
-                        for (int g = 0; g < 4; ++g) {
-                            S *p = tp + mtile_off((ip + ib) * 16 + lr, jb * 16 + 4 * lk + g);
-                            __builtin_nontemporal_store(__builtin_nontemporal_load(p) - acc[jb][ib][g], p);
-                        }
+                        for (int g = 0; g < 4; ++g)
+                            c[jb][g] = __builtin_nontemporal_load(tp + mtile_off((ip + ib) * 16 + lr, jb * 16 + 4 * lk + g));
+#pragma unroll
+                    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+                        for (int g = 0; g < 4; ++g)
+                            __builtin_nontemporal_store(c[jb][g] - acc[jb][ib][g],
+                                                        tp + mtile_off((ip + ib) * 16 + lr, jb * 16 + 4 * lk + g));
+                }
             }
         }
     }
@@ -517,9 +600,7 @@ struct Band {
         int *prog = reinterpret_cast<int *>(scratch + NWAVE * 4 * BW);
         if (tid < NWAVE) prog[tid] = (tid - NWAVE) * 4096 + 4095;
         __syncthreads();
-        const int i = lane & 31, hh = lane >> 5;
         double *vp = scratch + wave * 4 * BW, *vc = vp + BW, *wv = vp + 2 * BW, *cs = vp + 3 * BW;
-        const int csel = (((lane >> 4) & 1) << 3) | (((lane >> 3) & 1) << 2) | (((lane >> 2) & 1) << 1) | ((lane >> 1) & 1);
         const int pw = (wave + NWAVE - 1) % NWAVE;
         for (int s = wave; s + 2 < m; s += NWAVE) {
             double taup = 0.0;
@@ -528,31 +609,42 @@ struct Band {
                 const int lo = s + 1 + t * BW;
                 if (lo > m - 1) break;
                 const int L = min(BW, m - lo);
+                // lane-dependent indices are recomputed every step (not hoisted and
+                // kept live across the sweep loops)
+                int ln = lane;
+                asm volatile("" : "+v"(ln));
+                const int i = ln & 31, hh = ln >> 5;
+                const int csel = (((ln >> 4) & 1) << 3) | (((ln >> 3) & 1) << 2) | (((ln >> 2) & 1) << 1) | ((ln >> 1) & 1);
                 if (s > 0) {
                     const int need = (s - 1) * 4096 + min(t + 2, 4095);
                     while (__atomic_load_n(&prog[pw], __ATOMIC_RELAXED) < need) __builtin_amdgcn_s_sleep(1);
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
                 }
                 // all loads of the step at once: the block below the previous
-                // diagonal block (or column s) and the diagonal block
+                // diagonal block (or column s) and the diagonal block.  Every lane
+                // loads (a dead entry from offset 0, then discarded): a load under a
+                // lane condition would make the compiler wait for the loads before it.
+                // Every lane loads its whole row of both blocks: entries outside the
+                // matrix are band storage that is never written (zero, the band has BW
+                // spare columns), so no load needs a lane condition.
                 double bk[16], dk[16];
                 double x = 0.0;
                 if (t == 0) {
-                    x = (i < L) ? bnd[(int64_t)s * BLD + (lo + i - s)] : 0.0;
+                    x = bnd[(unsigned)(s * BLD + 1 + i)];                    // A(lo + i, s)
                 } else {
+                    // A(lo + i, plo + c): entry BW + i - c of band column plo + c
+                    const double *pb = bnd + (unsigned)(plo * BLD + BW + i + (BLD - 1) * hh * 16);
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) bk[q] = pb[(BLD - 1) * q];
+                }
+                {
+                    // D(i, c) = A(lo + max, lo + min): entry |i - c| of band column lo + min(i, c)
+                    const unsigned b1 = (unsigned)(lo * BLD + i), b2 = (unsigned)(lo * BLD + (BLD - 1) * i);
 #pragma unroll
                     for (int q = 0; q < 16; ++q) {
                         const int c = hh * 16 + q;
-                        bk[q] = (i < L && c < pL) ? bnd[(int64_t)(plo + c) * BLD + (lo + i - plo - c)] : 0.0;
+                        dk[q] = bnd[(c <= i) ? b1 + (unsigned)((BLD - 1) * c) : b2 + (unsigned)c];
                     }
-                }
-#pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const int c = hh * 16 + q;
-                    double d = 0.0;
-                    if (L >= 2 && i < L && c < L)
-                        d = (c <= i) ? bnd[(int64_t)(lo + c) * BLD + (i - c)] : bnd[(int64_t)(lo + i) * BLD + (c - i)];
-                    dk[q] = d;
                 }
                 // publish the previous step: its stores complete together with these loads
                 if (t > 0) {
@@ -586,9 +678,9 @@ struct Band {
                     v = (i == 0) ? 1.0 : 0.0;
                 }
                 if (hh == 0) vc[i] = v;
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
                 if (t == 0) {
-                    if (hh == 0 && i < L) bnd[(int64_t)s * BLD + (lo + i - s)] = (i == 0) ? beta : 0.0;
+                    if (hh == 0 && i < L) bnd[(unsigned)(s * BLD + 1 + i)] = (i == 0) ? beta : 0.0;
                 } else {
                     // left-apply to the columns 1.. of the block; column 0 becomes beta e0
                     double p[16];
@@ -596,12 +688,13 @@ struct Band {
                     for (int q = 0; q < 16; ++q) p[q] = v * bk[q];
                     const double sum = colsum32(p);
                     if ((lane & 1) == 0) cs[hh * 16 + csel] = sum;
-                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    double *pb = bnd + (unsigned)(plo * BLD + BW + i + (BLD - 1) * hh * 16);
 #pragma unroll
                     for (int q = 0; q < 16; ++q) {
                         const int c = hh * 16 + q;
                         bk[q] = (c == 0) ? ((i == 0) ? beta : 0.0) : fma(-tau * v, cs[c], bk[q]);
-                        if (i < L && c < pL) bnd[(int64_t)(plo + c) * BLD + (lo + i - plo - c)] = bk[q];
+                        if (i < L && c < pL) pb[(BLD - 1) * q] = bk[q];
                     }
                 }
                 if (L < 2) break;
@@ -614,16 +707,17 @@ struct Band {
                 const double kap = 0.5 * tau * wave_sum((hh == 0) ? v * w0 : 0.0);
                 const double w = fma(-kap, v, w0);
                 if (hh == 0) wv[i] = w;
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                double *pd = bnd + (unsigned)(lo * BLD + i + (BLD - 1) * hh * 16);
 #pragma unroll
                 for (int q = 0; q < 16; ++q) {
                     const int c = hh * 16 + q;
                     dk[q] -= fma(v, wv[c], w * vc[c]);
-                    if (i < L && c <= i) bnd[(int64_t)(lo + c) * BLD + (i - c)] = dk[q];
+                    if (i < L && c <= i) pd[(BLD - 1) * q] = dk[q];   // lower triangle: A(lo + i, lo + c)
                 }
                 // this reflector is applied from the right in the next step
                 if (hh == 0) vp[i] = v;
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
                 taup = tau;
                 plo = lo;
                 pL = L;
@@ -647,7 +741,7 @@ __host__ __device__ inline int64_t slot_bytes_band(int LDmax) {
     const int64_t T = LDmax / TILE;
     const int64_t tiles = T * (T + 1) / 2 * TILE_ELEMS * (int64_t)sizeof(S);
     const int64_t panel = 2 * (int64_t)BW * LDmax * 8;
-    const int64_t band = (int64_t)LDmax * BLD * 8;
+    const int64_t band = (int64_t)(LDmax + BW) * BLD * 8;
     const int64_t de = 2 * (int64_t)LDmax * 8;
     return ((tiles + 255) / 256) * 256 + panel + band + de;
 }
@@ -699,7 +793,7 @@ void band_bisect_kernel(TriArgs args) {
         t.V = reinterpret_cast<double *>(slot + tile_bytes);
         t.Wm = t.V + (int64_t)BW * t.LD;
         t.bnd = t.Wm + (int64_t)BW * t.LD;
-        t.dg = t.bnd + (int64_t)BLD * t.LD;
+        t.dg = t.bnd + (int64_t)BLD * (t.LD + BW);
         t.eg = t.dg + t.LD;
         t.gather(it);
         __syncthreads();

@@ -27,7 +27,7 @@ EXPORTS = (
     "eeid_components", "eeid_components_subset", "eeid_all_components", "eeid_set_graph_mode",
     "eeid_autotune",
 )
-VARIANTS = ("nb32_nt512", "nb32_nt256x2", "nb16_nt512", "band32_nt512")
+VARIANTS = ("nb32_nt512", "nb32_nt256x2", "nb16_nt512", "band32_nt512", "band32_nt256x2")
 
 
 class EEIDError(RuntimeError):
