@@ -98,34 +98,41 @@ struct Band {
     // column c is brought up to date with the reflectors 0..c-1 of the panel
     // (x = P(:,c) - V T^T V^T P(:,c)), then reflector c annihilates x below row
     // r0 + c.  R goes to the band, v_c to V(:, c) (v_c(r0 + c) = 1), T to LDS.
+    // Two block barriers per column: pass A (writes v_{c-1}, reduces V^T x_c and
+    // V^T v_{c-1}), then every wave forms column c-1 of T and t = T^T V^T x_c
+    // itself; pass B (x_c - V t, |x|^2), then every thread forms the reflector.
     __device__ void panel_qr(int k0) {
         const int r0 = k0 + BW;
-        double *tv = vec;           // t = T^T V^T x (BW)
-        double *sc = vec + 64;      // scalars: [0] tau, [1] scal, [2] alpha
+        double *zt = Nm + wave * 2 * BW;   // this wave's copies of z (V^T x) and t
+        double *sc = vec + 64;             // [2] alpha of the current column
+        double tau_p = 0.0, scal_p = 0.0;  // reflector c - 1 (uniform)
         for (int c = 0; c <= BW; ++c) {
-            // ---- pass A: z = V(:,0:c)^T x_c, g = V(:,0:c-1)^T v_{c-1}
+            // ---- pass A
             double accz = 0.0, accg = 0.0;
             for (int r0i = r0; r0i < m; r0i += NT) {
                 asm volatile("" ::: "memory");
                 const int r = r0i + tid;
                 const bool live = r < m;
+                // all 32 columns of V are loaded at once (columns >= c - 1 are still
+                // zero): loads under a condition would be waited for one chunk at a time
+                const int rl = live ? r : r0;
                 double vr[BW];
 #pragma unroll
-                for (int l = 0; l < BW; ++l) vr[l] = 0.0;
+                for (int l = 0; l < BW; ++l) vr[l] = V[(int64_t)l * LD + rl];
+                const double xr = Mget(rl, k0 + min(c, BW - 1));
+                const double wr = Wm[(int64_t)max(c - 1, 0) * LD + rl];
+                __builtin_amdgcn_sched_barrier(0);  // every load above is in flight before any use
                 double x = 0.0, vp = 0.0;
                 if (live) {
-#pragma unroll
-                    for (int q = 0; q < BW / 8; ++q)
-                        if (q * 8 < c) {
-#pragma unroll
-                            for (int l = q * 8; l < q * 8 + 8; ++l) vr[l] = V[(int64_t)l * LD + r];
-                        }
-                    if (c < BW) x = Mget(r, k0 + c);
-                    if (c > 0) vp = V[(int64_t)(c - 1) * LD + r];
+                    if (c < BW) x = xr;
+                    if (c > 0 && r >= r0 + c - 1) {
+                        vp = (r == r0 + c - 1) ? 1.0 : wr * scal_p;
+                        V[(int64_t)(c - 1) * LD + r] = vp;
+                    }
                 }
                 double wz[BW];
 #pragma unroll
-                for (int l = 0; l < BW; ++l) wz[l] = (l < c) ? vr[l] * x : 0.0;
+                for (int l = 0; l < BW; ++l) wz[l] = (l + 1 < c) ? vr[l] * x : ((l + 1 == c) ? vp * x : 0.0);
                 accz += wave_transpose_sum<BW>(wz, lane);
 #pragma unroll
                 for (int l = 0; l < BW; ++l) wz[l] = (l + 1 < c) ? vr[l] * vp : 0.0;
@@ -134,33 +141,35 @@ struct Band {
             to_red(accz, 0);
             to_red(accg, BW);
             __syncthreads();
-            if (wave == 0) {
+            // ---- every wave: z, g; column c-1 of T; t = T(0:c, 0:c)^T z
+            {
                 double z = 0.0, g = 0.0;
                 if (lane < BW)
                     for (int w = 0; w < NWAVE; ++w) { z += red[w * RED + lane]; g += red[w * RED + BW + lane]; }
-                // T(0:c-1, c-1) = -tau_{c-1} T(0:c-1, 0:c-1) g
+                if (lane < BW) { zt[lane] = z; zt[BW + lane] = g; }
+                __builtin_amdgcn_wave_barrier();
+                double tnew = 0.0;  // T(lane, c - 1)
                 if (c > 0) {
-                    if (lane < BW) tv[lane] = g;
-                    __builtin_amdgcn_wave_barrier();  // LDS accesses of one wave complete in order
-                    const double tau = Tm[(c - 1) * BW + (c - 1)];
+                    if (lane < c - 1) {
+                        double s = 0.0;
+                        for (int l = lane; l < c - 1; ++l) s = fma(Tm[lane * BW + l], zt[BW + l], s);
+                        tnew = -tau_p * s;
+                    } else if (lane == c - 1) {
+                        tnew = tau_p;
+                    }
+                    if (wave == 0 && lane < c) Tm[lane * BW + (c - 1)] = tnew;
+                }
+                if (c < BW) {
                     double s = 0.0;
                     if (lane < c - 1)
-                        for (int l = lane; l < c - 1; ++l) s = fma(Tm[lane * BW + l], tv[l], s);
-                    if (lane < c - 1) Tm[lane * BW + (c - 1)] = -tau * s;
-                }
-                __builtin_amdgcn_wave_barrier();
-                if (c < BW) {
-                    // t = T(0:c, 0:c)^T z
-                    if (lane < BW) tv[BW + lane] = z;
+                        for (int l = 0; l <= lane; ++l) s = fma(Tm[l * BW + lane], zt[l], s);
+                    // column c - 1 of T is still in registers (tnew): t(c-1) = sum_l T(l, c-1) z_l
+                    const double tc = wave_sum((lane < c) ? tnew * z : 0.0);
                     __builtin_amdgcn_wave_barrier();
-                    double s = 0.0;
-                    if (lane < c)
-                        for (int l = 0; l <= lane; ++l) s = fma(Tm[l * BW + lane], tv[BW + l], s);
+                    if (lane < BW) zt[lane] = (lane < c - 1) ? s : ((lane == c - 1) ? tc : 0.0);
                     __builtin_amdgcn_wave_barrier();
-                    if (lane < BW) tv[lane] = (lane < c) ? s : 0.0;
                 }
             }
-            __syncthreads();
             if (c == BW) break;
             // ---- pass B: x = P(:,c) - V t; R entries above the diagonal to the band,
             //      alpha = x(r0 + c), sigma = |x(r0+c+1:)|^2, x(r0+c+1:) kept in Wm(:, c)
@@ -169,13 +178,15 @@ struct Band {
                 asm volatile("" ::: "memory");
                 const int r = r0i + tid;
                 if (r < m) {
-                    double s = Mget(r, k0 + c);
+                    double vr[BW];
 #pragma unroll
-                    for (int q = 0; q < BW / 8; ++q)
-                        if (q * 8 < c) {
+                    for (int l = 0; l < BW; ++l) vr[l] = V[(int64_t)l * LD + r];
+                    const double x0 = Mget(r, k0 + c);
+                    __builtin_amdgcn_sched_barrier(0);
+                    double s4[4] = {x0, 0.0, 0.0, 0.0};
 #pragma unroll
-                            for (int l = q * 8; l < q * 8 + 8; ++l) s = fma(-V[(int64_t)l * LD + r], tv[l], s);
-                        }
+                    for (int l = 0; l < BW; ++l) s4[l & 3] = fma(-vr[l], zt[l], s4[l & 3]);  // zt[l >= c] = 0
+                    const double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
                     const int rr = r - r0;
                     if (rr < c) bnd[(int64_t)(k0 + c) * BLD + (r - k0 - c)] = s;      // R(rr, c)
                     else if (rr == c) sc[2] = s;
@@ -185,7 +196,7 @@ struct Band {
             sig = wave_sum(sig);
             if (lane == 0) red[wave * RED + 2 * BW] = sig;
             __syncthreads();
-            if (tid == 0) {
+            {   // ---- every thread: reflector c
                 double sg = 0.0;
                 for (int w = 0; w < NWAVE; ++w) sg += red[w * RED + 2 * BW];
                 double tau = 0.0, scal = 0.0;
@@ -198,21 +209,15 @@ struct Band {
                         tau = (beta - alpha) / beta;
                         scal = 1.0 / (alpha - beta);
                     }
-                    bnd[(int64_t)(k0 + c) * BLD + BW] = beta;   // R(c, c) = A(r0 + c, k0 + c)
+                    if (tid == 0) bnd[(int64_t)(k0 + c) * BLD + BW] = beta;   // R(c, c) = A(r0 + c, k0 + c)
                 }
-                Tm[c * BW + c] = tau;
-                sc[0] = tau;
-                sc[1] = scal;
+                tau_p = tau;
+                scal_p = scal;
             }
-            __syncthreads();
-            // ---- pass C: v_c
-            {
-                const double scal = sc[1];
-                for (int r = r0 + c + tid; r < m; r += NT)
-                    V[(int64_t)c * LD + r] = (r == r0 + c) ? 1.0 : Wm[(int64_t)c * LD + r] * scal;
-            }
-            __syncthreads();
+            // the next pass A reads red[] and sc[] only after its own writes to red[], which
+            // follow this read in every wave: no barrier needed here
         }
+        __syncthreads();
     }
 
     // ---------------------------------------------------------------- SYMM
@@ -362,6 +367,7 @@ struct Band {
             double yr[BW];
 #pragma unroll
             for (int l = 0; l < BW; ++l) yr[l] = Wm[(int64_t)l * LD + r];
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int l = BW - 1; l >= 0; --l) {
                 double s = 0.0;
@@ -418,6 +424,7 @@ struct Band {
             double vr[BW], xr[BW];
 #pragma unroll
             for (int l = 0; l < BW; ++l) { vr[l] = V[(int64_t)l * LD + r]; xr[l] = Wm[(int64_t)l * LD + r]; }
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int l = 0; l < BW; ++l) {
                 double s = 0.0;
