@@ -55,7 +55,7 @@ struct eeid_handle_s {
     int *counter = nullptr;
     std::vector<int64_t> items_key, desc_key, desc_sub_key;
     int64_t n_items = 0;
-    int variant = 0;            // real-kernel configuration when the tune table has no entry
+    int variant = -1;           // >= 0: real-kernel configuration when the tune table has no entry
     int forced_variant = -1;    // >= 0: use this configuration (autotuning, EEID_VARIANT)
     int64_t max_slots = 0;      // > 0: cap on resident problems (EEID_MAX_SLOTS)
     uint64_t generation = 0;    // bumped whenever a buffer the kernels read is reallocated or rewritten
@@ -212,7 +212,10 @@ int pick_variant(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64_t nmax, i
     if (h->forced_variant >= 0) return h->forced_variant;
     for (const auto &e : h->tune)
         if (e[0] == t && e[1] == p && e[2] == nmax && e[3] == problems) return (int)e[4];
-    return h->variant;
+    if (h->variant >= 0) return h->variant;
+    // untuned default (measured on the n = 64 ... 2048 workloads): the two-stage
+    // reduction, one problem per CU from n = 1024 on, two per CU below
+    return (nmax >= 1024) ? 3 : 4;
 }
 
 // kind 0: eigenvalues of the matrices only; kind 1: matrices and all minors;

@@ -438,7 +438,7 @@ struct Band {
     // ---------------------------------------------------------------- SYR2K
     // C(I, J) -= V_I W_J^T + W_I V_J^T for tiles J >= J1, J-side rows staged in
     // LDS per tile column (column k of the panel at vs[k*64 + row]).
-    __device__ void syr2k_tile(int I, const double *vs, const double *ws, int J) {
+    __device__ void syr2k_tile(int I, const double *vs, const double *ws, int J, int sld) {
         S *tp = tile_ptr(I, J);
         const int lr = lane & 15, lk = lane >> 4;
         const double *vI = V + I * TILE + lr, *wI = Wm + I * TILE + lr;
@@ -453,7 +453,7 @@ struct Band {
 #pragma unroll 2
                 for (int kk = 0; kk < BW; kk += 4) {
                     const int64_t col = (int64_t)(kk + lk) * LD;
-                    const int sc = (kk + lk) * TILE + lr;
+                    const int64_t sc = (int64_t)(kk + lk) * sld + lr;
                     double aw[4], av[4], bv[2], bw[2];
 #pragma unroll
                     for (int q = 0; q < 2; ++q) { bv[q] = vI[col + (ip + q) * 16]; bw[q] = wI[col + (ip + q) * 16]; }
@@ -497,7 +497,7 @@ struct Band {
 #pragma unroll 2
                 for (int kk = 0; kk < BW; kk += 4) {
                     const int64_t col = (int64_t)(kk + lk) * LD;
-                    const int sc = (kk + lk) * TILE + lr;
+                    const int64_t sc = (int64_t)(kk + lk) * sld + lr;
                     float aw[4], av[4], bv[2], bw[2];
 #pragma unroll
                     for (int q = 0; q < 2; ++q) {
@@ -546,7 +546,7 @@ struct Band {
                 ws[q] = Wm[(int64_t)kc * LD + J * TILE + r];
             }
             __syncthreads();
-            for (int I = J + wave; I < T; I += NWAVE) syr2k_tile(I, vs, ws, J);
+            for (int I = J + wave; I < T; I += NWAVE) syr2k_tile(I, vs, ws, J, TILE);
             __syncthreads();
         }
     }
