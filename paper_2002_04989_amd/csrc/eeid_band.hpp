@@ -94,129 +94,137 @@ struct Band {
         if ((lane & 1) == 0) red[wave * RED + off + (lane >> 1)] = acc;
     }
 
-    // Left-looking Householder QR of P = A(r0:m, k0:k0+BW), r0 = k0 + BW:
-    // column c is brought up to date with the reflectors 0..c-1 of the panel
-    // (x = P(:,c) - V T^T V^T P(:,c)), then reflector c annihilates x below row
-    // r0 + c.  R goes to the band, v_c to V(:, c) (v_c(r0 + c) = 1), T to LDS.
-    // Two block barriers per column: pass A (writes v_{c-1}, reduces V^T x_c and
-    // V^T v_{c-1}), then every wave forms column c-1 of T and t = T^T V^T x_c
-    // itself; pass B (x_c - V t, |x|^2), then every thread forms the reflector.
+    // Left-looking Householder QR of P = A(r0:m, k0:k0+BW), r0 = k0 + BW, in
+    // compact WY form I - V T V^T.  Column c is brought up to date with the
+    // reflectors 0..c-1 of the panel, x_c = P(:,c) - V T^T V^T P(:,c), and
+    // reflector c annihilates x_c below row r0 + c: v_c = e_{r0+c} + s_c x_c(below)
+    // with s_c = 1 / (alpha - beta).  One pass over the rows per column forms
+    // x_c and, looking ahead, every sum the next column needs:
+    //   V^T P(:,c+1) for columns 0..c-1 of V, and x_c(below) . P(:,c+1) (gives
+    //   v_c . P(:,c+1) once s_c is known);
+    //   V^T x_c(below) (gives V^T v_c, hence column c of T).
+    // One block barrier per column; every wave then forms reflector c, column c
+    // of T and t = T^T V^T P(:,c+1) itself.  R goes to the band, v_c to V(:, c)
+    // (written by the owner of each row at the start of the next pass), T to
+    // LDS.
     __device__ void panel_qr(int k0) {
         const int r0 = k0 + BW;
-        double *zt = Nm + wave * 2 * BW;   // this wave's copies of z (V^T x) and t
-        double *sc = vec + 64;             // [2] alpha of the current column
-        double tau_p = 0.0, scal_p = 0.0;  // reflector c - 1 (uniform)
-        for (int c = 0; c <= BW; ++c) {
-            // ---- pass A
-            double accz = 0.0, accg = 0.0;
+        double *zt = Nm + wave * 2 * BW;   // this wave's z = V^T P(:, c+1) and t = T^T z
+        double scal_p = 0.0;               // s_{c-1} (uniform)
+        if (lane < 2 * BW) zt[lane] = 0.0;
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll 1
+        for (int c = 0; c < BW; ++c) {
+            const bool more = c + 1 < BW;
+            // partial sums and scalars alternate between two LDS buffers by column
+            // parity, so one barrier per column suffices: a wave writes the other
+            // buffer while slower waves still read this one
+            double *rd = (c & 1) ? Mm : red;
+            double *sc = vec + 64 + (c & 1) * 40;  // [0] alpha_c, [1] P(r0+c, c+1), [2..) V(r0+c, 0..c-1)
+            double accq = 0.0, accg = 0.0, sig = 0.0, dx = 0.0;
             for (int r0i = r0; r0i < m; r0i += NT) {
                 asm volatile("" ::: "memory");
                 const int r = r0i + tid;
                 const bool live = r < m;
-                // all 32 columns of V are loaded at once (columns >= c - 1 are still
-                // zero): loads under a condition would be waited for one chunk at a time
                 const int rl = live ? r : r0;
+                // v_{c-1} at this row (x_{c-1} was kept in Wm(:, c-1))
+                double vprev = 0.0;
+                if (c > 0 && live && r >= r0 + c - 1) {
+                    vprev = (r == r0 + c - 1) ? 1.0 : Wm[(int64_t)(c - 1) * LD + r] * scal_p;
+                    V[(int64_t)(c - 1) * LD + r] = vprev;
+                }
+                const double p0 = Mget(rl, k0 + c);
+                const double p1 = Mget(rl, k0 + min(c + 1, BW - 1));
                 double vr[BW];
 #pragma unroll
-                for (int l = 0; l < BW; ++l) vr[l] = V[(int64_t)l * LD + rl];
-                const double xr = Mget(rl, k0 + min(c, BW - 1));
-                const double wr = Wm[(int64_t)max(c - 1, 0) * LD + rl];
-                __builtin_amdgcn_sched_barrier(0);  // every load above is in flight before any use
-                double x = 0.0, vp = 0.0;
+                for (int l = 0; l < BW; ++l) vr[l] = V[(int64_t)l * LD + rl];   // columns >= c are 0
+                __builtin_amdgcn_sched_barrier(0);   // (v_{c-1} was stored above by this thread)
+                double s4[4] = {p0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int l = 0; l < BW; ++l) s4[l & 3] = fma(-vr[l], zt[BW + l], s4[l & 3]);  // t[l >= c] = 0
+                const double xc = live ? (s4[0] + s4[1]) + (s4[2] + s4[3]) : 0.0;
+                const double xn = (live && more) ? p1 : 0.0;
+                const int rr = r - r0;
+                const bool below = live && rr > c;
                 if (live) {
-                    if (c < BW) x = xr;
-                    if (c > 0 && r >= r0 + c - 1) {
-                        vp = (r == r0 + c - 1) ? 1.0 : wr * scal_p;
-                        V[(int64_t)(c - 1) * LD + r] = vp;
+                    if (rr < c) bnd[(int64_t)(k0 + c) * BLD + (r - k0 - c)] = xc;      // R(rr, c)
+                    else if (rr == c) {
+                        sc[0] = xc;
+                        sc[1] = xn;
+#pragma unroll
+                        for (int l = 0; l < BW; ++l) sc[2 + l] = vr[l];
+                    } else {
+                        Wm[(int64_t)c * LD + r] = xc;
                     }
                 }
+                const double xb = below ? xc : 0.0;
+                sig = fma(xb, xb, sig);
+                dx = fma(xb, xn, dx);
                 double wz[BW];
 #pragma unroll
-                for (int l = 0; l < BW; ++l) wz[l] = (l + 1 < c) ? vr[l] * x : ((l + 1 == c) ? vp * x : 0.0);
-                accz += wave_transpose_sum<BW>(wz, lane);
+                for (int l = 0; l < BW; ++l) wz[l] = vr[l] * xn;       // V^T P(:, c+1), l < c
+                accq += wave_transpose_sum<BW>(wz, lane);
 #pragma unroll
-                for (int l = 0; l < BW; ++l) wz[l] = (l + 1 < c) ? vr[l] * vp : 0.0;
+                for (int l = 0; l < BW; ++l) wz[l] = vr[l] * xb;       // V^T x_c(below), l < c
                 accg += wave_transpose_sum<BW>(wz, lane);
             }
-            to_red(accz, 0);
-            to_red(accg, BW);
-            __syncthreads();
-            // ---- every wave: z, g; column c-1 of T; t = T(0:c, 0:c)^T z
-            {
-                double z = 0.0, g = 0.0;
-                if (lane < BW)
-                    for (int w = 0; w < NWAVE; ++w) { z += red[w * RED + lane]; g += red[w * RED + BW + lane]; }
-                if (lane < BW) { zt[lane] = z; zt[BW + lane] = g; }
-                __builtin_amdgcn_wave_barrier();
-                double tnew = 0.0;  // T(lane, c - 1)
-                if (c > 0) {
-                    if (lane < c - 1) {
-                        double s = 0.0;
-                        for (int l = lane; l < c - 1; ++l) s = fma(Tm[lane * BW + l], zt[BW + l], s);
-                        tnew = -tau_p * s;
-                    } else if (lane == c - 1) {
-                        tnew = tau_p;
-                    }
-                    if (wave == 0 && lane < c) Tm[lane * BW + (c - 1)] = tnew;
-                }
-                if (c < BW) {
-                    double s = 0.0;
-                    if (lane < c - 1)
-                        for (int l = 0; l <= lane; ++l) s = fma(Tm[l * BW + lane], zt[l], s);
-                    // column c - 1 of T is still in registers (tnew): t(c-1) = sum_l T(l, c-1) z_l
-                    const double tc = wave_sum((lane < c) ? tnew * z : 0.0);
-                    __builtin_amdgcn_wave_barrier();
-                    if (lane < BW) zt[lane] = (lane < c - 1) ? s : ((lane == c - 1) ? tc : 0.0);
-                    __builtin_amdgcn_wave_barrier();
-                }
-            }
-            if (c == BW) break;
-            // ---- pass B: x = P(:,c) - V t; R entries above the diagonal to the band,
-            //      alpha = x(r0 + c), sigma = |x(r0+c+1:)|^2, x(r0+c+1:) kept in Wm(:, c)
-            double sig = 0.0;
-            for (int r0i = r0; r0i < m; r0i += NT) {
-                asm volatile("" ::: "memory");
-                const int r = r0i + tid;
-                if (r < m) {
-                    double vr[BW];
-#pragma unroll
-                    for (int l = 0; l < BW; ++l) vr[l] = V[(int64_t)l * LD + r];
-                    const double x0 = Mget(r, k0 + c);
-                    __builtin_amdgcn_sched_barrier(0);
-                    double s4[4] = {x0, 0.0, 0.0, 0.0};
-#pragma unroll
-                    for (int l = 0; l < BW; ++l) s4[l & 3] = fma(-vr[l], zt[l], s4[l & 3]);  // zt[l >= c] = 0
-                    const double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
-                    const int rr = r - r0;
-                    if (rr < c) bnd[(int64_t)(k0 + c) * BLD + (r - k0 - c)] = s;      // R(rr, c)
-                    else if (rr == c) sc[2] = s;
-                    else { sig = fma(s, s, sig); Wm[(int64_t)c * LD + r] = s; }
-                }
-            }
             sig = wave_sum(sig);
-            if (lane == 0) red[wave * RED + 2 * BW] = sig;
+            dx = wave_sum(dx);
+            if ((lane & 1) == 0) { rd[wave * RED + (lane >> 1)] = accq; rd[wave * RED + BW + (lane >> 1)] = accg; }
+            if (lane == 0) { rd[wave * RED + 2 * BW] = sig; rd[wave * RED + 2 * BW + 1] = dx; }
             __syncthreads();
-            {   // ---- every thread: reflector c
-                double sg = 0.0;
-                for (int w = 0; w < NWAVE; ++w) sg += red[w * RED + 2 * BW];
-                double tau = 0.0, scal = 0.0;
-                if (r0 + c < m) {
-                    const double alpha = sc[2];
-                    double beta = alpha;
-                    if (sg != 0.0) {
-                        const double nrm = sqrt(fma(alpha, alpha, sg));
-                        beta = (alpha >= 0.0) ? -nrm : nrm;
-                        tau = (beta - alpha) / beta;
-                        scal = 1.0 / (alpha - beta);
-                    }
-                    if (tid == 0) bnd[(int64_t)(k0 + c) * BLD + BW] = beta;   // R(c, c) = A(r0 + c, k0 + c)
+            // ---- every wave: reflector c, column c of T, t for column c + 1
+            double sg = 0.0, dxt = 0.0;
+            for (int w = 0; w < NWAVE; ++w) { sg += rd[w * RED + 2 * BW]; dxt += rd[w * RED + 2 * BW + 1]; }
+            double tau = 0.0, scal = 0.0;
+            if (r0 + c < m) {
+                const double alpha = sc[0];
+                double beta = alpha;
+                if (sg != 0.0) {
+                    const double nrm = sqrt(fma(alpha, alpha, sg));
+                    beta = (alpha >= 0.0) ? -nrm : nrm;
+                    tau = (beta - alpha) / beta;
+                    scal = 1.0 / (alpha - beta);
                 }
-                tau_p = tau;
-                scal_p = scal;
+                if (tid == 0) bnd[(int64_t)(k0 + c) * BLD + BW] = beta;   // R(c, c) = A(r0 + c, k0 + c)
             }
-            // the next pass A reads red[] and sc[] only after its own writes to red[], which
-            // follow this read in every wave: no barrier needed here
+            {
+                double q = 0.0, g = 0.0;
+                if (lane < BW)
+                    for (int w = 0; w < NWAVE; ++w) { q += rd[w * RED + lane]; g += rd[w * RED + BW + lane]; }
+                // V^T v_c (l < c) and z = V(:,0:c+1)^T P(:,c+1)
+                const bool has = r0 + c < m;
+                const double gl = (lane < c && has) ? sc[2 + lane] + scal * g : 0.0;
+                const double zl = (lane < c) ? q : ((lane == c && has) ? sc[1] + scal * dxt : 0.0);
+                if (lane < BW) zt[lane] = gl;
+                __builtin_amdgcn_wave_barrier();
+                // column c of T: T(l, c) = -tau T(l, l..c-1) (V^T v_c)(l..c-1), T(c, c) = tau
+                double tcol = 0.0;
+                if (lane < c) {
+                    double s = 0.0;
+                    for (int l = lane; l < c; ++l) s = fma(Tm[lane * BW + l], zt[l], s);
+                    tcol = -tau * s;
+                } else if (lane == c) {
+                    tcol = tau;
+                }
+                if (wave == 0 && lane <= c) Tm[lane * BW + c] = tcol;
+                // t = T(0:c+1, 0:c+1)^T z: columns < c of T from LDS, column c from tcol
+                __builtin_amdgcn_wave_barrier();
+                if (lane < BW) zt[lane] = zl;
+                __builtin_amdgcn_wave_barrier();
+                double t = 0.0;
+                if (lane < c)
+                    for (int l = 0; l <= lane; ++l) t = fma(Tm[l * BW + lane], zt[l], t);
+                const double tc = wave_sum((lane <= c) ? tcol * zl : 0.0);
+                __builtin_amdgcn_wave_barrier();
+                if (lane < BW) zt[BW + lane] = (lane < c) ? t : ((lane == c) ? tc : 0.0);
+                __builtin_amdgcn_wave_barrier();
+            }
+            scal_p = scal;
         }
+        // v_{BW-1}
+        for (int r = r0 + BW - 1 + tid; r < m; r += NT)
+            V[(int64_t)(BW - 1) * LD + r] = (r == r0 + BW - 1) ? 1.0 : Wm[(int64_t)(BW - 1) * LD + r] * scal_p;
         __syncthreads();
     }
 
