@@ -167,6 +167,17 @@ eeid_status_t eeid_all_components(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p
 /* Enable (1) or disable (0) graph mode for eeid_all_components. */
 eeid_status_t eeid_set_graph_mode(eeid_handle_t h, int enable);
 
+/* Number of compiled configurations of the real eigenvalue kernel (the
+ * complex kernel has one).  Configurations 0..2 use the one-stage Householder
+ * reduction, 3..4 the two-stage (dense -> band -> tridiagonal) reduction. */
+int eeid_variant_count(void);
+
+/* Use configuration `variant` (0 .. eeid_variant_count() - 1) of the real
+ * eigenvalue kernel for every real batch on this handle, or restore the
+ * automatic choice (tune table, else a size rule) with variant = -1.
+ * Returns EEID_ERR_INVALID_ARG for any other value. */
+eeid_status_t eeid_set_variant(eeid_handle_t h, int variant);
+
 /* Time every compiled configuration of the eigenvalue kernel on this batch
  * (one eeid_minor_eigvals each, outputs written to lambda/mu/flags) and use
  * the fastest for batches of the same dtype, precision, largest order and

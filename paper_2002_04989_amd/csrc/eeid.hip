@@ -486,6 +486,16 @@ eeid_status_t eeid_set_graph_mode(eeid_handle_t h, int enable) {
     return EEID_OK;
 }
 
+int eeid_variant_count(void) { return N_REAL_VARIANTS; }
+
+eeid_status_t eeid_set_variant(eeid_handle_t h, int variant) {
+    if (!h) return EEID_ERR_INVALID_ARG;
+    if (variant < -1 || variant >= N_REAL_VARIANTS)
+        return fail(h, EEID_ERR_INVALID_ARG, "variant out of range");
+    h->forced_variant = variant;
+    return EEID_OK;
+}
+
 const char *eeid_status_string(eeid_status_t s) {
     switch (s) {
         case EEID_OK: return "EEID_OK: success";

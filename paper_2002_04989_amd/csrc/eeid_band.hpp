@@ -24,10 +24,12 @@
 // are those of the problem up to backward-stable rounding.
 //
 // Trailing-matrix storage (S = double or float): the lower triangle in 64x64
-// tiles as in eeid_tridiag.hpp, but inside a tile 16x16 sub-blocks, sub-block
-// (sr, sc) at (sc * 4 + sr) * 256, column-major inside a sub-block: element
-// (r, c) at ((c / 16) * 4 + r / 16) * 256 + (c % 16) * 16 + r % 16.  Each
-// matrix-core operand then loads as 512 contiguous bytes (FP64).
+// tiles as in eeid_tridiag.hpp, but inside a tile 8x4 micro-tiles (8 rows,
+// 4 columns, column-major inside), micro-tile (mr, mc) at (mc * 8 + mr) * 32:
+// element (r, c) at ((c / 4) * 8 + r / 8) * 32 + (c % 4) * 8 + r % 8.  The
+// operands of one matrix-core step are then whole micro-tiles in every pass:
+// 32 rows x 4 columns (row pass: 1 KiB contiguous), 8 rows x 16 columns
+// (column pass: four 256-byte runs), 16 rows x 4 columns (update: 512 bytes).
 // Band storage: column c holds A(c + d, c), d in [0, 2 BW), at bnd[c * BLD + d]
 // (the chase leaves fill up to d = 2 BW - 1 during a step), for LD + BW
 // columns; entries outside the matrix stay zero.  The trailing
@@ -42,7 +44,7 @@ constexpr int BW = 32;        // half-bandwidth of the intermediate band = panel
 constexpr int BLD = 2 * BW;   // band storage per column
 
 __device__ __forceinline__ int mtile_off(int r, int c) {
-    return (((c >> 4) << 2) + (r >> 4)) * 256 + ((c & 15) << 4) + (r & 15);
+    return (((c >> 2) << 3) + (r >> 3)) * 32 + ((c & 3) << 3) + (r & 7);
 }
 
 template <class S, int NT>
@@ -71,8 +73,8 @@ struct Band {
             for (int I = J; I < T; ++I) {
                 S *tp = tile_ptr(I, J);
                 for (int q = tid; q < TILE_ELEMS; q += NT) {
-                    const int sb = q >> 8, in = q & 255;
-                    const int r = ((sb & 3) << 4) + (in & 15), c = ((sb >> 2) << 4) + (in >> 4);
+                    const int mt = q >> 5, in = q & 31;   // micro-tile, element inside it
+                    const int r = ((mt & 7) << 3) + (in & 7), c = ((mt >> 3) << 2) + (in >> 3);
                     const int row = I * TILE + r, col = J * TILE + c;
                     double v = 0.0;
                     if (row < m && col < m) {

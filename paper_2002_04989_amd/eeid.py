@@ -25,6 +25,7 @@ EXPORTS = (
     "eeid_create", "eeid_destroy", "eeid_set_stream", "eeid_status_string", "eeid_last_error",
     "eeid_eigvalsh_batched", "eeid_minor_eigvals", "eeid_minor_eigvals_subset",
     "eeid_components", "eeid_components_subset", "eeid_all_components", "eeid_set_graph_mode",
+    "eeid_variant_count", "eeid_set_variant",
     "eeid_autotune",
 )
 VARIANTS = ("nb32_nt512", "nb32_nt256x2", "nb16_nt512", "band32_nt512", "band32_nt256x2")
@@ -67,6 +68,9 @@ def load_library(path: str = LIB_PATH):
     lib.eeid_all_components.argtypes = [_vp, c, c, ctypes.c_int64, _i64p, _i64p, _vp, _vp, _vp, _vp, _vp]
     lib.eeid_components_subset.argtypes = [_vp, ctypes.c_int64, _vp, ctypes.c_int64, _vp, _vp, _vp]
     lib.eeid_set_graph_mode.argtypes = [_vp, c]
+    lib.eeid_variant_count.argtypes = []
+    lib.eeid_variant_count.restype = c
+    lib.eeid_set_variant.argtypes = [_vp, c]
     lib.eeid_autotune.argtypes = [_vp, c, c, ctypes.c_int64, _i64p, _i64p, _vp, _vp, _vp, _vp,
                                   ctypes.POINTER(c), ctypes.POINTER(ctypes.c_double)]
     for name in EXPORTS:
@@ -213,6 +217,13 @@ def set_graph_mode(enable: bool, device: int | None = None):
     """Record eeid_all_components into a hipGraph per argument set and replay it."""
     h = handle(device)
     _check(load_library().eeid_set_graph_mode(h, 1 if enable else 0), h)
+
+
+def set_variant(variant, device: int | None = None):
+    """Force a real-kernel configuration (name from VARIANTS or index), or None for automatic."""
+    h = handle(device)
+    v = -1 if variant is None else (VARIANTS.index(variant) if isinstance(variant, str) else int(variant))
+    _check(load_library().eeid_set_variant(h, v), h)
 
 
 def autotune(mats, prec: str = "fp64"):

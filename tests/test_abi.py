@@ -14,7 +14,7 @@ HEADER = os.path.join(ROOT, "include", "eeid.h")
 
 def declared_functions():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:const char \*|eeid_status_t)\s*(eeid_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:const char \*|eeid_status_t|int)\s*(eeid_\w+)\s*\(", text, re.M)))
 
 
 def test_header_compiles_as_c99(tmp_path):
@@ -60,6 +60,12 @@ def test_null_handle_is_invalid_argument():
     assert lib.eeid_set_stream(None, None) == 1
     assert lib.eeid_last_error(None) == b""
     assert lib.eeid_create(None, 0) == 1
+    assert lib.eeid_set_variant(None, 0) == 1
+
+
+def test_variant_table_matches_binding():
+    lib = eeid.load_library()
+    assert lib.eeid_variant_count() == len(eeid.VARIANTS)
 
 
 def test_no_device_is_reported(monkeypatch):

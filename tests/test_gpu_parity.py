@@ -170,6 +170,30 @@ def test_fp32_trailing_form_error_is_bounded():
     assert flag == 0
 
 
+@pytest.mark.parametrize("variant", ["nb32_nt512", "nb32_nt256x2", "nb16_nt512", "band32_nt512", "band32_nt256x2"])
+def test_every_real_kernel_configuration(variant):
+    """Each compiled configuration (one-stage and two-stage reductions) in one
+    uneven batch that spans one tile, several tiles and panels and ragged tails,
+    in the FP64 form (oracle tolerances) and the FP32-trailing form (a-priori
+    bound)."""
+    from paper_2002_04989_amd import eeid
+    announce(f"kernel configuration {variant}")
+    mats = [inputs.goe(n, 900 + n) for n in (2, 17, 64, 97, 130)] + [inputs.wishart(161, 8)]
+    eeid.set_variant(variant)
+    try:
+        for A, got in zip(mats, run_all(mats, "fp64")):
+            check(A, got)
+        for A, (lam, mu, W, flag) in zip(mats, run_all(mats, "fp32")):
+            n = A.shape[0]
+            lam_o, mu_o, _, _ = oracle.components_identity(A, js=[0, n - 1])
+            s = norm2(A)
+            bound = 8 * np.sqrt(n) * 2.0 ** -24
+            assert np.max(np.abs(lam - lam_o)) / s < bound and flag == 0
+            assert np.max(np.abs(mu[[0, n - 1]] - mu_o)) / s < bound
+    finally:
+        eeid.set_variant(None)
+
+
 # ------------------------------------------------------------ complex Hermitian
 @pytest.mark.parametrize("n", [1, 2, 3, 17, 33, 64, 65, 100, 130])
 def test_gue_sizes(n):
