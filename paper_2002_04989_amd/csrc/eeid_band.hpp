@@ -594,14 +594,25 @@ struct Band {
     }
 
     // --------------------------------------------------------------- stage 2
-    // Bulge chasing, one sweep per wave: wave w takes sweeps w, w + NWAVE, ...
-    // Step t of sweep s acts on rows s + 1 + t BW .. s + (t + 1) BW, which were
-    // last written by sweep s - 1 in its steps t and t + 1; step t + 2 of sweep
-    // s - 1 touches only rows below that, so sweep s runs two steps behind
-    // sweep s - 1.  Progress counters in LDS (sweep * 4096 + steps done, 4095
-    // when the sweep is complete) order the waves; band writes are released
-    // and acquired at workgroup scope around them.
-    // Lane l holds row i = l % 32 of a BW x BW block and its columns
+    // Bulge chasing.  Sweep s removes column s below the subdiagonal; its step t
+    // acts on rows lo .. lo + 31, lo = s + 1 + 32 t: the previous reflector is
+    // applied from the right to the block B = A(lo.., lo-32..) below the
+    // previous diagonal block, the first column of B is annihilated by a new
+    // reflector that is applied to the rest of B and two-sidedly to the diagonal
+    // block D = A(lo.., lo..).  (Step 0 annihilates column s itself.)
+    //
+    // Sweeps run in pairs (s, s + 1), s even, one pair per wave, pair p on wave
+    // p mod NWAVE.  Step t of sweep s + 1 acts on the blocks of step t of sweep s
+    // shifted down and right by one, plus the first row of step t + 1 of sweep s;
+    // the rest of its last row is zero (annihilated by earlier sweeps).  So the
+    // wave runs sweep s one step ahead and builds the blocks of sweep s + 1 in
+    // registers: sweep s loads its blocks, sweep s + 1 stores its results, and
+    // the band makes one trip through memory per pair of sweeps.  Sweep s of a
+    // pair waits for the second sweep of the previous pair to have finished its
+    // steps t and t + 1 (progress counters in LDS, sweep * 4096 + steps done,
+    // 4095 when complete, ordered by workgroup-scope release and acquire).
+    //
+    // Lane l holds row i = l % 32 of a 32 x 32 block and its columns
     // 16 h .. 16 h + 15, h = l / 32.
     __device__ double colsum32(double (&p)[16]) {
         // sum of p[q] over the 32 lanes of this half; returns the sum of column
@@ -613,134 +624,223 @@ struct Band {
         return p[0] + __shfl_xor(p[0], 1);
     }
 
+    // Per-sweep LDS vectors of one wave.
+    struct ChaseVecs { double *vp, *vc, *wv, *cs; };
+
+    // One step on blocks held in registers.  first: step 0 (x = column s given,
+    // no B block).  Otherwise the previous reflector (vp, taup) is applied to B
+    // from the right and x is B's first column.  On return: bk = B with column 0
+    // = beta e0 (not first), dk = D updated, vc = new reflector, vp = vc, taup =
+    // tau; beta returned.  L rows of the step exist (L < 2: only the right
+    // application is done).
+    __device__ double chase_compute(bool first, double x, double (&bk)[16], double (&dk)[16], int L, double &taup,
+                                    const ChaseVecs &cv, int i, int hh, int csel) {
+        if (!first) {
+            double u = 0.0;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) u = fma(bk[q], cv.vp[hh * 16 + q], u);
+            u += __shfl_xor(u, 32);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) bk[q] = fma(-taup * u, cv.vp[hh * 16 + q], bk[q]);
+            x = __shfl(bk[0], i);  // column 0 of the block: lane i of half 0
+        }
+        double tau = 0.0, beta, v;
+        if (L >= 2) {
+            const double alpha = __shfl(x, 0);
+            const double sg = wave_sum((hh == 0 && i >= 1 && i < L) ? x * x : 0.0);
+            double scal = 0.0;
+            beta = alpha;
+            if (sg != 0.0) {
+                const double nrm = sqrt(fma(alpha, alpha, sg));
+                beta = (alpha >= 0.0) ? -nrm : nrm;
+                tau = (beta - alpha) / beta;
+                scal = 1.0 / (alpha - beta);
+            }
+            v = (i == 0) ? 1.0 : ((i < L) ? x * scal : 0.0);
+        } else {
+            beta = __shfl(x, 0);
+            v = (i == 0) ? 1.0 : 0.0;
+        }
+        if (hh == 0) cv.vc[i] = v;
+        __builtin_amdgcn_wave_barrier();
+        if (!first) {
+            // left application to the columns 1.. of B; column 0 becomes beta e0
+            double p[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) p[q] = v * bk[q];
+            const double sum = colsum32(p);
+            if ((lane & 1) == 0) cv.cs[hh * 16 + csel] = sum;
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int c = hh * 16 + q;
+                bk[q] = (c == 0) ? ((i == 0) ? beta : 0.0) : fma(-tau * v, cv.cs[c], bk[q]);
+            }
+        }
+        if (L >= 2) {
+            // two-sided update of the diagonal block
+            double pr = 0.0;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) pr = fma(dk[q], cv.vc[hh * 16 + q], pr);
+            pr += __shfl_xor(pr, 32);
+            const double w0 = tau * pr;
+            const double kap = 0.5 * tau * wave_sum((hh == 0) ? v * w0 : 0.0);
+            const double w = fma(-kap, v, w0);
+            if (hh == 0) cv.wv[i] = w;
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int c = hh * 16 + q;
+                dk[q] -= fma(v, cv.wv[c], w * cv.vc[c]);
+            }
+            if (hh == 0) cv.vp[i] = v;   // applied from the right in the next step
+            __builtin_amdgcn_wave_barrier();
+        }
+        taup = tau;
+        return beta;
+    }
+
+    // Stores of a step of sweep `sw` at rows lo..: column sw (first step) or B,
+    // and the lower triangle of D.
+    __device__ void chase_store(bool first, int sw, int lo, int L, int pL, double beta, const double (&bk)[16],
+                                const double (&dk)[16], int i, int hh) {
+        if (first) {
+            if (hh == 0 && i < L) bnd[(unsigned)(sw * BLD + 1 + i)] = (i == 0) ? beta : 0.0;
+        } else {
+            double *pb = bnd + (unsigned)((lo - BW) * BLD + BW + i + (BLD - 1) * hh * 16);
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+                if (i < L && hh * 16 + q < pL) pb[(BLD - 1) * q] = bk[q];
+        }
+        {   // (also for L = 1: in a pair the diagonal entry may come from the other sweep)
+            double *pd = bnd + (unsigned)(lo * BLD + i + (BLD - 1) * hh * 16);
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+                if (i < L && hh * 16 + q <= i) pd[(BLD - 1) * q] = dk[q];   // A(lo + i, lo + c), c <= i
+        }
+    }
+
     __device__ void band_to_tridiagonal(double *scratch) {
-        int *prog = reinterpret_cast<int *>(scratch + NWAVE * 4 * BW);
-        if (tid < NWAVE) prog[tid] = (tid - NWAVE) * 4096 + 4095;
+        constexpr int PER_WAVE = 8 * BW + 40;
+        int *prog = reinterpret_cast<int *>(scratch + NWAVE * PER_WAVE);
+        if (tid < NWAVE) prog[tid] = (2 * (tid - NWAVE) + 1) * 4096 + 4095;
         __syncthreads();
-        double *vp = scratch + wave * 4 * BW, *vc = vp + BW, *wv = vp + 2 * BW, *cs = vp + 3 * BW;
+        double *ws = scratch + wave * PER_WAVE;
+        const ChaseVecs cvL{ws, ws + BW, ws + 2 * BW, ws + 3 * BW};
+        const ChaseVecs cvF{ws + 4 * BW, ws + 5 * BW, ws + 6 * BW, ws + 7 * BW};
+        double *row0 = ws + 8 * BW;   // first row of the current step of sweep s, then D(0, 0)
         const int pw = (wave + NWAVE - 1) % NWAVE;
-        for (int s = wave; s + 2 < m; s += NWAVE) {
-            double taup = 0.0;
-            int plo = 0, pL = 0;
+        for (int s = 2 * wave; s + 2 < m; s += 2 * NWAVE) {
+            const int sf = s + 1;
+            const bool pair = sf + 2 < m;
+            double taupL = 0.0, taupF = 0.0;
+            double pb[16], pd[16];   // sweep s, previous step
+#pragma unroll
+            for (int q = 0; q < 16; ++q) { pb[q] = 0.0; pd[q] = 0.0; }
+            int tf = -1;            // last step of sweep s + 1 done
             for (int t = 0;; ++t) {
                 const int lo = s + 1 + t * BW;
-                if (lo > m - 1) break;
-                const int L = min(BW, m - lo);
+                const bool lead = lo <= m - 1;
                 // lane-dependent indices are recomputed every step (not hoisted and
                 // kept live across the sweep loops)
                 int ln = lane;
                 asm volatile("" : "+v"(ln));
                 const int i = ln & 31, hh = ln >> 5;
                 const int csel = (((ln >> 4) & 1) << 3) | (((ln >> 3) & 1) << 2) | (((ln >> 2) & 1) << 1) | ((ln >> 1) & 1);
-                if (s > 0) {
-                    const int need = (s - 1) * 4096 + min(t + 2, 4095);
-                    while (__atomic_load_n(&prog[pw], __ATOMIC_RELAXED) < need) __builtin_amdgcn_s_sleep(1);
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                }
-                // all loads of the step at once: the block below the previous
-                // diagonal block (or column s) and the diagonal block.  Every lane
-                // loads (a dead entry from offset 0, then discarded): a load under a
-                // lane condition would make the compiler wait for the loads before it.
-                // Every lane loads its whole row of both blocks: entries outside the
-                // matrix are band storage that is never written (zero, the band has BW
-                // spare columns), so no load needs a lane condition.
-                double bk[16], dk[16];
-                double x = 0.0;
-                if (t == 0) {
-                    x = bnd[(unsigned)(s * BLD + 1 + i)];                    // A(lo + i, s)
-                } else {
-                    // A(lo + i, plo + c): entry BW + i - c of band column plo + c
-                    const double *pb = bnd + (unsigned)(plo * BLD + BW + i + (BLD - 1) * hh * 16);
+                double cb[16], cd[16];   // sweep s, this step
+                double x = 0.0, betaL = 0.0;
+                const int L = lead ? min(BW, m - lo) : 0;
+                if (lead) {
+                    if (s > 0) {
+                        const int need = (s - 1) * 4096 + min(t + 2, 4095);
+                        while (__atomic_load_n(&prog[pw], __ATOMIC_RELAXED) < need) __builtin_amdgcn_s_sleep(1);
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                    }
+                    // all loads of the step at once; entries outside the matrix are
+                    // band storage that is never written (zero)
+                    if (t == 0) {
+                        x = bnd[(unsigned)(s * BLD + 1 + i)];                  // A(lo + i, s)
+                    } else {
+                        const double *pbp = bnd + (unsigned)((lo - BW) * BLD + BW + i + (BLD - 1) * hh * 16);
 #pragma unroll
-                    for (int q = 0; q < 16; ++q) bk[q] = pb[(BLD - 1) * q];
-                }
-                {
-                    // D(i, c) = A(lo + max, lo + min): entry |i - c| of band column lo + min(i, c)
+                        for (int q = 0; q < 16; ++q) cb[q] = pbp[(BLD - 1) * q];
+                    }
                     const unsigned b1 = (unsigned)(lo * BLD + i), b2 = (unsigned)(lo * BLD + (BLD - 1) * i);
 #pragma unroll
                     for (int q = 0; q < 16; ++q) {
                         const int c = hh * 16 + q;
-                        dk[q] = bnd[(c <= i) ? b1 + (unsigned)((BLD - 1) * c) : b2 + (unsigned)c];
+                        cd[q] = bnd[(c <= i) ? b1 + (unsigned)((BLD - 1) * c) : b2 + (unsigned)c];
                     }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) { cb[q] = 0.0; cd[q] = 0.0; }
                 }
-                // publish the previous step: its stores complete together with these loads
-                if (t > 0) {
+                // publish the steps of sweep s + 1 stored so far (they complete with these loads)
+                if (tf >= 0) {
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                    if (lane == 0) __atomic_store_n(&prog[wave], s * 4096 + t, __ATOMIC_RELAXED);
+                    if (lane == 0) __atomic_store_n(&prog[wave], sf * 4096 + tf + 1, __ATOMIC_RELAXED);
                 }
-                if (t > 0) {
-                    double u = 0.0;
-#pragma unroll
-                    for (int q = 0; q < 16; ++q) u = fma(bk[q], vp[hh * 16 + q], u);
-                    u += __shfl_xor(u, 32);
-#pragma unroll
-                    for (int q = 0; q < 16; ++q) bk[q] = fma(-taup * u, vp[hh * 16 + q], bk[q]);
-                    x = __shfl(bk[0], i);  // column 0 of the block: lane i of half 0
-                }
-                double tau = 0.0, beta = 0.0, v = 0.0;
-                if (L >= 2) {
-                    const double alpha = __shfl(x, 0);
-                    const double sg = wave_sum((hh == 0 && i >= 1 && i < L) ? x * x : 0.0);
-                    double scal = 0.0;
-                    beta = alpha;
-                    if (sg != 0.0) {
-                        const double nrm = sqrt(fma(alpha, alpha, sg));
-                        beta = (alpha >= 0.0) ? -nrm : nrm;
-                        tau = (beta - alpha) / beta;
-                        scal = 1.0 / (alpha - beta);
+                if (lead) {
+                    betaL = chase_compute(t == 0, x, cb, cd, L, taupL, cvL, i, hh, csel);
+                    if (!pair) {
+                        chase_store(t == 0, s, lo, L, BW, betaL, cb, cd, i, hh);
+                    } else if (t == 0) {
+                        // column s and A(s + 1, s + 1) are final; the rest of this step
+                        // continues in sweep s + 1
+                        if (hh == 0 && i < L) bnd[(unsigned)(s * BLD + 1 + i)] = (i == 0) ? betaL : 0.0;
+                        if (lane == 0) bnd[(unsigned)(lo * BLD)] = cd[0];
+                    } else {
+                        // the annihilated first column of B below its first row is not part
+                        // of any block of sweep s + 1 (later sweeps read it as zero)
+                        if (hh == 0 && i >= 1 && i < L) bnd[(unsigned)((lo - BW) * BLD + BW + i)] = 0.0;
                     }
-                    v = (i == 0) ? 1.0 : ((i < L) ? x * scal : 0.0);
-                } else {
-                    beta = __shfl(x, 0);
-                    v = (i == 0) ? 1.0 : 0.0;
                 }
-                if (hh == 0) vc[i] = v;
-                __builtin_amdgcn_wave_barrier();
-                if (t == 0) {
-                    if (hh == 0 && i < L) bnd[(unsigned)(s * BLD + 1 + i)] = (i == 0) ? beta : 0.0;
-                } else {
-                    // left-apply to the columns 1.. of the block; column 0 becomes beta e0
-                    double p[16];
+                // ---- step t - 1 of sweep s + 1, from steps t - 1 (pb, pd) and t (cb, cd) of sweep s
+                const int lof = s + 2 + (t - 1) * BW;
+                if (pair && t >= 1 && lof <= m - 1) {
+                    const int Lf = min(BW, m - lof);
+                    // first row of this step of sweep s (cols lo - 32 .. lo - 1) and its D(0, 0)
+                    if (i == 0) {
 #pragma unroll
-                    for (int q = 0; q < 16; ++q) p[q] = v * bk[q];
-                    const double sum = colsum32(p);
-                    if ((lane & 1) == 0) cs[hh * 16 + csel] = sum;
+                        for (int q = 0; q < 16; ++q) row0[hh * 16 + q] = cb[q];
+                    }
+                    if (lane == 0) row0[BW] = cd[0];
                     __builtin_amdgcn_wave_barrier();
-                    double *pb = bnd + (unsigned)(plo * BLD + BW + i + (BLD - 1) * hh * 16);
+                    // shift left by one column.  Column 15 of the lower half takes column 16
+                    // from the upper half; column 31 takes D(i, 0) of the previous step (block
+                    // B) or the row just computed, row0[i] (block D; D is symmetric).
+                    const double sb = __shfl_xor(pb[0], 32);   // lower half: B(i, 16)
+                    const double sd = __shfl_xor(pd[0], 32);   // lower half: D(i, 16); upper half: D(i, 0)
+                    double fb[16], fd[16];
+#pragma unroll
+                    for (int q = 0; q < 15; ++q) { fb[q] = pb[q + 1]; fd[q] = pd[q + 1]; }
+                    fb[15] = hh ? sd : sb;
+                    fd[15] = hh ? row0[i] : sd;
+                    // shift up by one row; row 31 of B is zero but for its last column,
+                    // row 31 of D is the first row of this step of sweep s
 #pragma unroll
                     for (int q = 0; q < 16; ++q) {
+                        const double nb = __shfl(fb[q], (lane & 32) | ((i + 1) & 31));
+                        const double nd = __shfl(fd[q], (lane & 32) | ((i + 1) & 31));
                         const int c = hh * 16 + q;
-                        bk[q] = (c == 0) ? ((i == 0) ? beta : 0.0) : fma(-tau * v, cs[c], bk[q]);
-                        if (i < L && c < pL) pb[(BLD - 1) * q] = bk[q];
+                        fb[q] = (i < 31) ? nb : ((c == 31) ? row0[0] : 0.0);
+                        fd[q] = (i < 31) ? nd : row0[c + 1];
                     }
+                    const bool ffirst = (t - 1 == 0);
+                    const double xf = ffirst ? fb[15] : 0.0;   // first step: column s + 1 is column 31
+                    const double xf0 = __shfl(xf, (i) | 32);    // held by the upper half
+                    const double betaF = chase_compute(ffirst, xf0, fb, fd, Lf, taupF, cvF, i, hh, csel);
+                    chase_store(ffirst, sf, lof, Lf, BW, betaF, fb, fd, i, hh);
+                    tf = t - 1;
                 }
-                if (L < 2) break;
-                // two-sided update of the diagonal block D = A(lo:lo+L, lo:lo+L)
-                double pr = 0.0;
+                // no later step of sweep s; then step t of sweep s + 1 would start at
+                // row lo + 1 > m - 1
+                if (!lead || L < 2) break;
 #pragma unroll
-                for (int q = 0; q < 16; ++q) pr = fma(dk[q], vc[hh * 16 + q], pr);
-                pr += __shfl_xor(pr, 32);
-                const double w0 = tau * pr;
-                const double kap = 0.5 * tau * wave_sum((hh == 0) ? v * w0 : 0.0);
-                const double w = fma(-kap, v, w0);
-                if (hh == 0) wv[i] = w;
-                __builtin_amdgcn_wave_barrier();
-                double *pd = bnd + (unsigned)(lo * BLD + i + (BLD - 1) * hh * 16);
-#pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const int c = hh * 16 + q;
-                    dk[q] -= fma(v, wv[c], w * vc[c]);
-                    if (i < L && c <= i) pd[(BLD - 1) * q] = dk[q];   // lower triangle: A(lo + i, lo + c)
-                }
-                // this reflector is applied from the right in the next step
-                if (hh == 0) vp[i] = v;
-                __builtin_amdgcn_wave_barrier();
-                taup = tau;
-                plo = lo;
-                pL = L;
+                for (int q = 0; q < 16; ++q) { pb[q] = cb[q]; pd[q] = cd[q]; }
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            if (lane == 0) __atomic_store_n(&prog[wave], s * 4096 + 4095, __ATOMIC_RELAXED);
+            if (lane == 0) __atomic_store_n(&prog[wave], sf * 4096 + 4095, __ATOMIC_RELAXED);
         }
         __syncthreads();
         for (int r = tid; r < m; r += NT) {
