@@ -137,9 +137,19 @@ struct Band {
                 }
                 const double p0 = Mget(rl, k0 + c);
                 const double p1 = Mget(rl, k0 + min(c + 1, BW - 1));
+                // only columns < c of V are nonzero: load them in chunks of 8 (the
+                // chunk count is uniform, so the loads stay unmasked and batched)
                 double vr[BW];
 #pragma unroll
-                for (int l = 0; l < BW; ++l) vr[l] = V[(int64_t)l * LD + rl];   // columns >= c are 0
+                for (int ch = 0; ch < BW / 8; ++ch) {
+                    if (ch * 8 < c) {
+#pragma unroll
+                        for (int l = ch * 8; l < ch * 8 + 8; ++l) vr[l] = V[(int64_t)l * LD + rl];
+                    } else {
+#pragma unroll
+                        for (int l = ch * 8; l < ch * 8 + 8; ++l) vr[l] = 0.0;
+                    }
+                }
                 __builtin_amdgcn_sched_barrier(0);   // (v_{c-1} was stored above by this thread)
                 double s4[4] = {p0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -621,7 +631,7 @@ struct Band {
         halve_step<8, 8>(p, lane);
         halve_step<4, 4>(p, lane);
         halve_step<2, 2>(p, lane);
-        return p[0] + __shfl_xor(p[0], 1);
+        return psum<1>(p[0]);
     }
 
     // Per-sweep LDS vectors of one wave.
@@ -639,14 +649,14 @@ struct Band {
             double u = 0.0;
 #pragma unroll
             for (int q = 0; q < 16; ++q) u = fma(bk[q], cv.vp[hh * 16 + q], u);
-            u += __shfl_xor(u, 32);
+            u = xsum32(u);
 #pragma unroll
             for (int q = 0; q < 16; ++q) bk[q] = fma(-taup * u, cv.vp[hh * 16 + q], bk[q]);
-            x = __shfl(bk[0], i);  // column 0 of the block: lane i of half 0
+            x = from_lower(bk[0]);  // column 0 of the block: lane i of half 0
         }
         double tau = 0.0, beta, v;
         if (L >= 2) {
-            const double alpha = __shfl(x, 0);
+            const double alpha = bcast0(x);
             const double sg = wave_sum((hh == 0 && i >= 1 && i < L) ? x * x : 0.0);
             double scal = 0.0;
             beta = alpha;
@@ -658,7 +668,7 @@ struct Band {
             }
             v = (i == 0) ? 1.0 : ((i < L) ? x * scal : 0.0);
         } else {
-            beta = __shfl(x, 0);
+            beta = bcast0(x);
             v = (i == 0) ? 1.0 : 0.0;
         }
         if (hh == 0) cv.vc[i] = v;
@@ -682,7 +692,7 @@ struct Band {
             double pr = 0.0;
 #pragma unroll
             for (int q = 0; q < 16; ++q) pr = fma(dk[q], cv.vc[hh * 16 + q], pr);
-            pr += __shfl_xor(pr, 32);
+            pr = xsum32(pr);
             const double w0 = tau * pr;
             const double kap = 0.5 * tau * wave_sum((hh == 0) ? v * w0 : 0.0);
             const double w = fma(-kap, v, w0);
@@ -809,8 +819,8 @@ struct Band {
                     // shift left by one column.  Column 15 of the lower half takes column 16
                     // from the upper half; column 31 takes D(i, 0) of the previous step (block
                     // B) or the row just computed, row0[i] (block D; D is symmetric).
-                    const double sb = __shfl_xor(pb[0], 32);   // lower half: B(i, 16)
-                    const double sd = __shfl_xor(pd[0], 32);   // lower half: D(i, 16); upper half: D(i, 0)
+                    const double sb = xswap32(pb[0], lane);   // lower half: B(i, 16)
+                    const double sd = xswap32(pd[0], lane);   // lower half: D(i, 16); upper half: D(i, 0)
                     double fb[16], fd[16];
 #pragma unroll
                     for (int q = 0; q < 15; ++q) { fb[q] = pb[q + 1]; fd[q] = pd[q + 1]; }
@@ -820,15 +830,15 @@ struct Band {
                     // row 31 of D is the first row of this step of sweep s
 #pragma unroll
                     for (int q = 0; q < 16; ++q) {
-                        const double nb = __shfl(fb[q], (lane & 32) | ((i + 1) & 31));
-                        const double nd = __shfl(fd[q], (lane & 32) | ((i + 1) & 31));
+                        const double nb = dpp_mov<DPP_WAVE_SHL1>(fb[q]);   // lane + 1 (rows 31 replaced)
+                        const double nd = dpp_mov<DPP_WAVE_SHL1>(fd[q]);
                         const int c = hh * 16 + q;
                         fb[q] = (i < 31) ? nb : ((c == 31) ? row0[0] : 0.0);
                         fd[q] = (i < 31) ? nd : row0[c + 1];
                     }
                     const bool ffirst = (t - 1 == 0);
                     const double xf = ffirst ? fb[15] : 0.0;   // first step: column s + 1 is column 31
-                    const double xf0 = __shfl(xf, (i) | 32);    // held by the upper half
+                    const double xf0 = from_upper(xf);    // held by the upper half
                     const double betaF = chase_compute(ffirst, xf0, fb, fd, Lf, taupF, cvF, i, hh, csel);
                     chase_store(ffirst, sf, lof, Lf, BW, betaF, fb, fd, i, hh);
                     tf = t - 1;

@@ -70,16 +70,112 @@ __device__ __forceinline__ int tile_off(int r, int c) {
     return (c / W) * (TILE * W) + r * W + (c % W);
 }
 
+// ---- cross-lane moves without the LDS crossbar
+// Within rows of 16 lanes a DPP move (quad permutations, row mirrors, and the
+// one-lane wave shift); across rows the lane-swap instructions of gfx950:
+// permlane32 swaps the upper half of its first operand with the lower half of
+// its second, permlane16 the odd rows of the first with the even rows of the
+// second.  A double moves as two dwords.
+enum : int {
+    DPP_XOR1 = 0xB1,         // quad_perm [1,0,3,2]: lane l ^ 1
+    DPP_XOR2 = 0x4E,         // quad_perm [2,3,0,1]: lane l ^ 2
+    DPP_MIRROR = 0x140,      // lane l ^ 15 within a row of 16
+    DPP_HALF_MIRROR = 0x141, // lane l ^ 7 within 8
+    DPP_WAVE_SHL1 = 0x130,   // lane l + 1 (lane 63 keeps its own value)
+};
+
+__device__ __forceinline__ unsigned lo32(double x) { return (unsigned)__builtin_bit_cast(unsigned long long, x); }
+__device__ __forceinline__ unsigned hi32(double x) { return (unsigned)(__builtin_bit_cast(unsigned long long, x) >> 32); }
+__device__ __forceinline__ double mk64(unsigned lo, unsigned hi) {
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double x) {
+    const unsigned lo = __builtin_amdgcn_update_dpp(lo32(x), lo32(x), CTRL, 0xf, 0xf, false);
+    const unsigned hi = __builtin_amdgcn_update_dpp(hi32(x), hi32(x), CTRL, 0xf, 0xf, false);
+    return mk64(lo, hi);
+}
+
+// Swap of a's upper 32 lanes with b's lower 32 lanes (OFF = 32) or of a's odd
+// rows with b's even rows (OFF = 16).  Afterwards, in every lane, a + b is the
+// lane's own a (lower half / even row) or own b (upper half / odd row) plus
+// the partner lane's (l ^ OFF) copy of the same operand.
+template <int OFF>
+__device__ __forceinline__ void lane_swap(double &a, double &b) {
+    static_assert(OFF == 16 || OFF == 32, "OFF");
+    if constexpr (OFF == 32) {
+        const auto l = __builtin_amdgcn_permlane32_swap(lo32(a), lo32(b), false, false);
+        const auto h = __builtin_amdgcn_permlane32_swap(hi32(a), hi32(b), false, false);
+        a = mk64(l[0], h[0]); b = mk64(l[1], h[1]);
+    } else {
+        const auto l = __builtin_amdgcn_permlane16_swap(lo32(a), lo32(b), false, false);
+        const auto h = __builtin_amdgcn_permlane16_swap(hi32(a), hi32(b), false, false);
+        a = mk64(l[0], h[0]); b = mk64(l[1], h[1]);
+    }
+}
+
+// x + x of lane l ^ 32, in every lane.
+__device__ __forceinline__ double xsum32(double x) { double a = x, b = x; lane_swap<32>(a, b); return a + b; }
+// x of lane l ^ 32.
+__device__ __forceinline__ double xswap32(double x, int lane) {
+    double a = x, b = x; lane_swap<32>(a, b); return (lane < 32) ? b : a;
+}
+// x of lane l % 32 (the lower half's copy) and of lane l % 32 + 32 (the upper half's).
+__device__ __forceinline__ double from_lower(double x) { double a = x, b = x; lane_swap<32>(a, b); return a; }
+__device__ __forceinline__ double from_upper(double x) { double a = x, b = x; lane_swap<32>(a, b); return b; }
+
+// x of lane 0, in every lane.
+__device__ __forceinline__ double bcast0(double x) {
+    return mk64(__builtin_amdgcn_readlane(lo32(x), 0), __builtin_amdgcn_readlane(hi32(x), 0));
+}
+
+// x combined with the copy of a partner lane that differs in bit OFF and in no
+// higher bit of the lane index (l ^ OFF for OFF = 32, 16, 2, 1; l ^ 15 for
+// OFF = 8, l ^ 7 for OFF = 4).  Applying it for OFF = 32, 16, ..., 1 combines
+// all 64 lanes: the partners' offsets 32, 16, 15, 7, 2, 1 span every index.
+template <int OFF>
+__device__ __forceinline__ double partner(double x) {
+    if constexpr (OFF == 8) return dpp_mov<DPP_MIRROR>(x);
+    else if constexpr (OFF == 4) return dpp_mov<DPP_HALF_MIRROR>(x);
+    else if constexpr (OFF == 2) return dpp_mov<DPP_XOR2>(x);
+    else {
+        static_assert(OFF == 1, "partner: OFF in {8, 4, 2, 1}");
+        return dpp_mov<DPP_XOR1>(x);
+    }
+}
+template <int OFF>
+__device__ __forceinline__ double psum(double x) {
+    if constexpr (OFF == 32 || OFF == 16) {
+        double a = x, b = x;
+        lane_swap<OFF>(a, b);
+        return a + b;
+    } else {
+        return x + partner<OFF>(x);
+    }
+}
+
 // One halving step: lanes with bit OFF set keep the upper half of v[0..CNT),
-// the others the lower half, each adding the partner lane's copy of that half.
+// the others the lower half, each adding the partner lane's copy of that half
+// (the partner differs in bit OFF and no higher bit, so it holds the same
+// entries of v).
 template <int CNT, int OFF, int N>
 __device__ __forceinline__ void halve_step(double (&v)[N], int lane) {
-    const bool hi = (lane & OFF) != 0;
+    if constexpr (OFF == 32 || OFF == 16) {
 #pragma unroll
-    for (int t = 0; t < CNT / 2; ++t) {
-        const double keep = hi ? v[CNT / 2 + t] : v[t];
-        const double send = hi ? v[t] : v[CNT / 2 + t];
-        v[t] = keep + __shfl_xor(send, OFF);
+        for (int t = 0; t < CNT / 2; ++t) {
+            double a = v[t], b = v[CNT / 2 + t];
+            lane_swap<OFF>(a, b);
+            v[t] = a + b;
+        }
+    } else {
+        const bool hi = (lane & OFF) != 0;
+#pragma unroll
+        for (int t = 0; t < CNT / 2; ++t) {
+            const double keep = hi ? v[CNT / 2 + t] : v[t];
+            const double send = hi ? v[t] : v[CNT / 2 + t];
+            v[t] = keep + partner<OFF>(send);
+        }
     }
 }
 
@@ -94,25 +190,32 @@ __device__ __forceinline__ double wave_transpose_sum(double (&v)[N], int lane) {
     halve_step<4, (N == 32 ? 4 : N == 16 ? 8 : 16)>(v, lane);
     halve_step<2, (N == 32 ? 2 : N == 16 ? 4 : 8)>(v, lane);
     double s = v[0];
-    if constexpr (N <= 16) s += __shfl_xor(s, N == 16 ? 2 : 4);
-    if constexpr (N <= 8) s += __shfl_xor(s, 2);
-    s += __shfl_xor(s, 1);
+    if constexpr (N <= 8) s = psum<4>(s);
+    if constexpr (N <= 16) s = psum<2>(s);
+    s = psum<1>(s);
     return s;
 }
 
 __device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off);
+    x = psum<32>(x); x = psum<16>(x); x = psum<8>(x); x = psum<4>(x); x = psum<2>(x); x = psum<1>(x);
     return x;
 }
+template <int OFF>
+__device__ __forceinline__ double pmin(double x) {
+    if constexpr (OFF == 32 || OFF == 16) { double a = x, b = x; lane_swap<OFF>(a, b); return fmin(a, b); }
+    else return fmin(x, partner<OFF>(x));
+}
+template <int OFF>
+__device__ __forceinline__ double pmax(double x) {
+    if constexpr (OFF == 32 || OFF == 16) { double a = x, b = x; lane_swap<OFF>(a, b); return fmax(a, b); }
+    else return fmax(x, partner<OFF>(x));
+}
 __device__ __forceinline__ double wave_min(double x) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) x = fmin(x, __shfl_xor(x, off));
+    x = pmin<32>(x); x = pmin<16>(x); x = pmin<8>(x); x = pmin<4>(x); x = pmin<2>(x); x = pmin<1>(x);
     return x;
 }
 __device__ __forceinline__ double wave_max(double x) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) x = fmax(x, __shfl_xor(x, off));
+    x = pmax<32>(x); x = pmax<16>(x); x = pmax<8>(x); x = pmax<4>(x); x = pmax<2>(x); x = pmax<1>(x);
     return x;
 }
 
