@@ -51,7 +51,7 @@ struct eeid_handle_s {
     hipStream_t stream = nullptr;
     int cu_count = 0;
     std::string err;
-    Buf work, items, desc, desc_sub, dpair, dpair_sub;
+    Buf work, items, desc, desc_sub, dpair, dpair_sub, lam_ready;
     int *counter = nullptr;
     std::vector<int64_t> items_key, desc_key, desc_sub_key;
     int64_t n_items = 0;
@@ -280,7 +280,12 @@ eeid_status_t prepare_eigs(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64
     s = ensure(h, h->work, (size_t)(slots * kc.slot));
     if (s != EEID_OK) return s;
 
+    s = ensure(h, h->lam_ready, sizeof(unsigned long long) * (size_t)count);
+    if (s != EEID_OK) return s;
+    unsigned long long *lam_ready = reinterpret_cast<unsigned long long *>(h->lam_ready.p);
+
     eeid::TriArgs a;
+    a.lam_ready = lam_ready;
     a.items = reinterpret_cast<const Item *>(h->items.p);
     a.n_items = h->n_items;
     a.counter = h->counter;
@@ -295,7 +300,7 @@ eeid_status_t prepare_eigs(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64
     const bool any_items = !items.empty();
     *out = [=](hipStream_t st) -> hipError_t {
         hipLaunchKernelGGL(eeid::prep_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, flags, count,
-                           (int *)nullptr);
+                           (int *)nullptr, lam_ready);
         hipLaunchKernelGGL(eeid::nonfinite_kernel, dim3(nn_blocks, (unsigned)count), dim3(256), 0, st, desc, Ad,
                            cplx, flags);
         if (!any_items) return hipGetLastError();
@@ -466,7 +471,7 @@ eeid_status_t eeid_destroy(eeid_handle_t h) {
     if (h->ev_in) (void)hipEventDestroy(h->ev_in);
     if (h->ev_out) (void)hipEventDestroy(h->ev_out);
     if (h->gstream) (void)hipStreamDestroy(h->gstream);
-    Buf *bufs[] = {&h->work, &h->items, &h->desc, &h->desc_sub, &h->dpair, &h->dpair_sub};
+    Buf *bufs[] = {&h->work, &h->items, &h->desc, &h->desc_sub, &h->dpair, &h->dpair_sub, &h->lam_ready};
     for (Buf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (h->counter) (void)hipFree(h->counter);

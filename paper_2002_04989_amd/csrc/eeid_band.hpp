@@ -860,7 +860,9 @@ struct Band {
         __syncthreads();
     }
 
-    __device__ void bisect(double *out) { bisect_tridiagonal<NT, 4>(dg, eg, m, out, de, red, tid, lane, wave); }
+    __device__ void bisect(double *out, const double *brk) {
+        bisect_tridiagonal<NT, 4>(dg, eg, m, out, de, red, tid, lane, wave, brk);
+    }
 };
 
 template <class S>
@@ -885,6 +887,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void band_bisect_kernel(TriArgs args) {
     extern __shared__ double lds[];
     __shared__ int s_item;
+    __shared__ unsigned long long s_flag;
     Band<S, NT> t;
     t.tid = threadIdx.x;
     t.lane = threadIdx.x & 63;
@@ -927,7 +930,8 @@ void band_bisect_kernel(TriArgs args) {
         t.reduce_to_band();
         __syncthreads();
         t.band_to_tridiagonal(t.Tm);
-        t.bisect(it.out);
+        t.bisect(it.out, interlacing_bracket(args, it, &s_flag));
+        publish_eigenvalues(args, it);
         __syncthreads();
     }
 }

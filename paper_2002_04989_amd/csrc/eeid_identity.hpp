@@ -31,9 +31,13 @@ __device__ __forceinline__ void neumaier_add(double &s, double &c, double x) {
     s = t;
 }
 
-__global__ __launch_bounds__(256) void prep_kernel(int32_t *flags, int64_t count, int *counter) {
+__global__ __launch_bounds__(256) void prep_kernel(int32_t *flags, int64_t count, int *counter,
+                                                   unsigned long long *lam_ready) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < count) flags[i] = 0;
+    if (i < count) {
+        flags[i] = 0;
+        if (lam_ready) lam_ready[i] = 0;
+    }
     if (i == 0 && counter) *counter = 0;
 }
 

@@ -238,9 +238,15 @@ struct Panel {
 // 80 halvings.  One lane per eigenvalue, ILP eigenvalues per lane in
 // lockstep; de (LDS, >= 2m doubles) receives (d_i, e_{i-1}^2) pairs, red
 // (LDS) the workgroup reductions.
+//
+// brk (optional): the m + 1 ascending eigenvalues of a matrix of which T is
+// similar to a principal minor.  By Cauchy interlacing eigenvalue k of the
+// minor lies in [brk[k], brk[k + 1]]; that interval, widened by the rounding
+// pad, is checked with two Sturm counts and replaces the Gershgorin interval
+// when the counts confirm it (else the Gershgorin interval is kept).
 template <int NT, int ILP>
 __device__ void bisect_tridiagonal(const double *dg, const double *eg, int m, double *out, double *de,
-                                   double *red, int tid, int lane, int wave) {
+                                   double *red, int tid, int lane, int wave, const double *brk = nullptr) {
     constexpr int NWAVE = NT / 64;
     double gl = 1e308, gu = -1e308, emax2 = 0.0;
     for (int i = tid; i < m; i += NT) {
@@ -278,15 +284,11 @@ __device__ void bisect_tridiagonal(const double *dg, const double *eg, int m, do
             lo[t] = gl; hi[t] = gu;
             done[t] = idx[t] >= m;
         }
-        for (int it = 0; it < 80; ++it) {
-            bool all = true;
+        // Sturm counts at ILP points
+        auto counts = [&](const double (&x)[ILP], int (&cnt)[ILP]) {
+            double q[ILP];
 #pragma unroll
-            for (int t = 0; t < ILP; ++t) all = all && done[t];
-            if (all) break;
-            double x[ILP], q[ILP];
-            int cnt[ILP];
-#pragma unroll
-            for (int t = 0; t < ILP; ++t) { x[t] = 0.5 * (lo[t] + hi[t]); q[t] = 1.0; cnt[t] = 0; }
+            for (int t = 0; t < ILP; ++t) { q[t] = 1.0; cnt[t] = 0; }
             for (int i = 0; i < m; ++i) {
                 const double d = de[2 * i], e2 = de[2 * i + 1];
 #pragma unroll
@@ -302,6 +304,32 @@ __device__ void bisect_tridiagonal(const double *dg, const double *eg, int m, do
                     q[t] = v;
                 }
             }
+        };
+        if (brk) {
+            double bl[ILP], bh[ILP];
+            int cl[ILP], ch[ILP];
+#pragma unroll
+            for (int t = 0; t < ILP; ++t) {
+                const int k = done[t] ? 0 : idx[t];
+                bl[t] = fmax(gl, brk[k] - pad);
+                bh[t] = fmin(gu, brk[k + 1] + pad);
+            }
+            counts(bl, cl);
+            counts(bh, ch);
+#pragma unroll
+            for (int t = 0; t < ILP; ++t)
+                if (!done[t] && bl[t] < bh[t] && cl[t] <= idx[t] && ch[t] > idx[t]) { lo[t] = bl[t]; hi[t] = bh[t]; }
+        }
+        for (int it = 0; it < 80; ++it) {
+            bool all = true;
+#pragma unroll
+            for (int t = 0; t < ILP; ++t) all = all && done[t];
+            if (all) break;
+            double x[ILP];
+            int cnt[ILP];
+#pragma unroll
+            for (int t = 0; t < ILP; ++t) x[t] = 0.5 * (lo[t] + hi[t]);
+            counts(x, cnt);
 #pragma unroll
             for (int t = 0; t < ILP; ++t) {
                 if (done[t]) continue;
@@ -799,7 +827,9 @@ struct Tri {
     }
 
     // ------------------------------------------------------------- bisection
-    __device__ void bisect(double *out) { bisect_tridiagonal<NT, BILP>(dg, eg, m, out, y, red, tid, lane, wave); }
+    __device__ void bisect(double *out, const double *brk) {
+        bisect_tridiagonal<NT, BILP>(dg, eg, m, out, y, red, tid, lane, wave, brk);
+    }
 };
 
 struct TriArgs {
@@ -810,7 +840,35 @@ struct TriArgs {
     char *work;
     int64_t slot_bytes;
     int LDmax;
+    // per batch: address of the matrix's own eigenvalues once they are final,
+    // else 0 (cleared before every launch)
+    unsigned long long *lam_ready;
 };
+
+// Bracket source for the bisection of item `it`: the eigenvalues of its
+// matrix if it is a minor and they are already final (published by the
+// workgroup that computed them), else nullptr.  Uniform over the workgroup;
+// s_flag is LDS scratch.
+__device__ inline const double *interlacing_bracket(const TriArgs &a, const Item &it, unsigned long long *s_flag) {
+    if (it.j < 0) return nullptr;
+    if (threadIdx.x == 0)
+        *s_flag = __hip_atomic_load(&a.lam_ready[it.b], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const unsigned long long p = *s_flag;
+    __syncthreads();
+    if (p == 0) return nullptr;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return reinterpret_cast<const double *>(p);
+}
+
+// After the eigenvalues of a matrix (it.j < 0) are stored: publish them.
+__device__ inline void publish_eigenvalues(const TriArgs &a, const Item &it) {
+    if (it.j >= 0) return;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0)
+        __hip_atomic_store(&a.lam_ready[it.b], (unsigned long long)it.out, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 template <class S, int NB>
 __host__ __device__ inline int64_t slot_bytes_for(int LDmax) {
@@ -837,6 +895,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 void tridiag_bisect_kernel(TriArgs args) {
     extern __shared__ double lds[];
     __shared__ int s_item;
+    __shared__ unsigned long long s_flag;
     Tri<S, NB, NT, CW, STAGE, (WPE >= 3 ? 2 : 4)> t;
     t.tid = threadIdx.x;
     t.lane = threadIdx.x & 63;
@@ -873,7 +932,8 @@ void tridiag_bisect_kernel(TriArgs args) {
         __syncthreads();
         t.tridiagonalize();
         __syncthreads();
-        t.bisect(it.out);
+        t.bisect(it.out, interlacing_bracket(args, it, &s_flag));
+        publish_eigenvalues(args, it);
         __syncthreads();
     }
 }

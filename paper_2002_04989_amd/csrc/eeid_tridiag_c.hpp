@@ -485,8 +485,8 @@ struct TriC {
         }
     }
 
-    __device__ void bisect(double *out) {
-        bisect_tridiagonal<NT, 4>(dg, eg, m, out, reinterpret_cast<double *>(y), red, tid, lane, wave);
+    __device__ void bisect(double *out, const double *brk) {
+        bisect_tridiagonal<NT, 4>(dg, eg, m, out, reinterpret_cast<double *>(y), red, tid, lane, wave, brk);
     }
 };
 
@@ -508,6 +508,7 @@ template <class R, int NB, int NT, int CW>
 __global__ __launch_bounds__(NT, 2) void tridiag_bisect_kernel_c(TriArgs args) {
     extern __shared__ double lds[];
     __shared__ int s_item;
+    __shared__ unsigned long long s_flag;
     TriC<R, NB, NT, CW> t;
     t.tid = threadIdx.x;
     t.lane = threadIdx.x & 63;
@@ -543,7 +544,8 @@ __global__ __launch_bounds__(NT, 2) void tridiag_bisect_kernel_c(TriArgs args) {
         __syncthreads();
         t.tridiagonalize();
         __syncthreads();
-        t.bisect(it.out);
+        t.bisect(it.out, interlacing_bracket(args, it, &s_flag));
+        publish_eigenvalues(args, it);
         __syncthreads();
     }
 }
