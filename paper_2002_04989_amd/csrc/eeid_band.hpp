@@ -611,16 +611,20 @@ struct Band {
     // reflector that is applied to the rest of B and two-sidedly to the diagonal
     // block D = A(lo.., lo..).  (Step 0 annihilates column s itself.)
     //
-    // Sweeps run in pairs (s, s + 1), s even, one pair per wave, pair p on wave
-    // p mod NWAVE.  Step t of sweep s + 1 acts on the blocks of step t of sweep s
-    // shifted down and right by one, plus the first row of step t + 1 of sweep s;
-    // the rest of its last row is zero (annihilated by earlier sweeps).  So the
-    // wave runs sweep s one step ahead and builds the blocks of sweep s + 1 in
-    // registers: sweep s loads its blocks, sweep s + 1 stores its results, and
-    // the band makes one trip through memory per pair of sweeps.  Sweep s of a
-    // pair waits for the second sweep of the previous pair to have finished its
-    // steps t and t + 1 (progress counters in LDS, sweep * 4096 + steps done,
-    // 4095 when complete, ordered by workgroup-scope release and acquire).
+    // Sweeps run in chains of CHAIN = 3 (s, s + 1, s + 2), one chain per wave,
+    // chain c on wave c mod NWAVE.  Step t of sweep s + 1 acts on the blocks of
+    // step t of sweep s shifted down and right by one, plus the first row of
+    // step t + 1 of sweep s; the rest of its last row is zero (annihilated by
+    // earlier sweeps).  So the wave runs sweep s + k one step behind sweep
+    // s + k - 1 and builds its blocks from those of sweep s + k - 1: sweep s
+    // loads its blocks, sweep s + 2 stores its results, and the band makes one
+    // trip through memory per chain.  The blocks of sweep s of the previous
+    // step stay in registers; those of sweep s + 1 wait in LDS for sweep s + 2.
+    // A sweep whose blocks pass on stores only what leaves them: the final
+    // column (first step) or the annihilated first column of B.  Sweep s of a
+    // chain waits for the last sweep of the previous chain to have finished
+    // its steps t and t + 1 (progress counters in LDS, sweep * 4096 + steps
+    // done, 4095 when complete, ordered by workgroup-scope release and acquire).
     //
     // Lane l holds row i = l % 32 of a 32 x 32 block and its columns
     // 16 h .. 16 h + 15, h = l / 32.
@@ -634,7 +638,8 @@ struct Band {
         return psum<1>(p[0]);
     }
 
-    // Per-sweep LDS vectors of one wave.
+    // LDS vectors of one wave: the previous reflector vp of a sweep, and the
+    // per-step temporaries vc, wv, cs (shared by the sweeps of a chain).
     struct ChaseVecs { double *vp, *vc, *wv, *cs; };
 
     // One step on blocks held in registers.  first: step 0 (x = column s given,
@@ -730,37 +735,94 @@ struct Band {
         }
     }
 
+    // Blocks (fb, fd) of step t of sweep s + 1 from the blocks (pb, pd) of step
+    // t of sweep s and row0 = the first row of step t + 1 of sweep s (B part,
+    // then D(0, 0) at row0[BW]).
+    __device__ void shift_blocks(const double (&pb)[16], const double (&pd)[16], const double *row0,
+                                 double (&fb)[16], double (&fd)[16], int i, int hh) {
+        // shift left by one column.  Column 15 of the lower half takes column 16
+        // from the upper half; column 31 takes D(i, 0) of the previous step (block
+        // B) or row0[i] (block D; D is symmetric).
+        const double sb = xswap32(pb[0], lane);   // lower half: B(i, 16)
+        const double sd = xswap32(pd[0], lane);   // lower half: D(i, 16); upper half: D(i, 0)
+#pragma unroll
+        for (int q = 0; q < 15; ++q) { fb[q] = pb[q + 1]; fd[q] = pd[q + 1]; }
+        fb[15] = hh ? sd : sb;
+        fd[15] = hh ? row0[i] : sd;
+        // shift up by one row; row 31 of B is zero but for its last column,
+        // row 31 of D is row0
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const double nb = dpp_mov<DPP_WAVE_SHL1>(fb[q]);   // lane + 1 (rows 31 replaced)
+            const double nd = dpp_mov<DPP_WAVE_SHL1>(fd[q]);
+            const int c = hh * 16 + q;
+            fb[q] = (i < 31) ? nb : ((c == 31) ? row0[0] : 0.0);
+            fd[q] = (i < 31) ? nd : row0[c + 1];
+        }
+    }
+
+    // Stores of a sweep whose blocks pass on to the next sweep of the chain:
+    // column sw and A(lo, lo) at its first step, else the annihilated first
+    // column of B below its first row.
+    __device__ void chase_store_passing(bool first, int sw, int lo, int L, double beta, double d00, int i, int hh) {
+        if (first) {
+            if (hh == 0 && i < L) bnd[(unsigned)(sw * BLD + 1 + i)] = (i == 0) ? beta : 0.0;
+            if (lane == 0) bnd[(unsigned)(lo * BLD)] = d00;
+        } else {
+            if (hh == 0 && i >= 1 && i < L) bnd[(unsigned)((lo - BW) * BLD + BW + i)] = 0.0;
+        }
+    }
+
+    // Row 0 of blocks (b, d) to LDS (B part, then D(0, 0) at row0[BW]).
+    __device__ void put_row0(double *row0, const double (&b)[16], const double (&d)[16], int i, int hh) {
+        if (i == 0) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) row0[hh * 16 + q] = b[q];
+        }
+        if (lane == 0) row0[BW] = d[0];
+        __builtin_amdgcn_wave_barrier();
+    }
+
+    static constexpr int CHAIN = 3;
+    // LDS doubles per wave: 3 vp + vc, wv, cs; two first rows; the saved blocks
+    static constexpr int CHASE_PER_WAVE = 6 * BW + 2 * 40 + 2 * 16 * 64;
+
     __device__ void band_to_tridiagonal(double *scratch) {
-        constexpr int PER_WAVE = 8 * BW + 40;
-        int *prog = reinterpret_cast<int *>(scratch + NWAVE * PER_WAVE);
-        if (tid < NWAVE) prog[tid] = (2 * (tid - NWAVE) + 1) * 4096 + 4095;
+        int *prog = reinterpret_cast<int *>(scratch + NWAVE * CHASE_PER_WAVE);
+        if (tid < NWAVE) prog[tid] = (CHAIN * (tid - NWAVE) + CHAIN - 1) * 4096 + 4095;
         __syncthreads();
-        double *ws = scratch + wave * PER_WAVE;
-        const ChaseVecs cvL{ws, ws + BW, ws + 2 * BW, ws + 3 * BW};
-        const ChaseVecs cvF{ws + 4 * BW, ws + 5 * BW, ws + 6 * BW, ws + 7 * BW};
-        double *row0 = ws + 8 * BW;   // first row of the current step of sweep s, then D(0, 0)
+        double *ws = scratch + wave * CHASE_PER_WAVE;
+        double *vc = ws + 3 * BW, *wv = ws + 4 * BW, *cs = ws + 5 * BW;
+        const ChaseVecs cv0{ws, vc, wv, cs}, cv1{ws + BW, vc, wv, cs}, cv2{ws + 2 * BW, vc, wv, cs};
+        double *row0a = ws + 6 * BW;        // first row of the current step of sweep s
+        double *row0b = row0a + 40;         // ... of sweep s + 1
+        double *saved = row0b + 40;         // blocks of sweep s + 1 of the previous step: [q * 64 + lane], D at + 1024
         const int pw = (wave + NWAVE - 1) % NWAVE;
-        for (int s = 2 * wave; s + 2 < m; s += 2 * NWAVE) {
-            const int sf = s + 1;
-            const bool pair = sf + 2 < m;
-            double taupL = 0.0, taupF = 0.0;
+        for (int s = CHAIN * wave; s + 2 < m; s += CHAIN * NWAVE) {
+            const bool has1 = s + 3 < m, has2 = s + 4 < m;
+            const int last0 = (m - 2 - s) / BW;
+            const int last1 = has1 ? (m - 3 - s) / BW : -1;
+            const int last2 = has2 ? (m - 4 - s) / BW : -1;
+            const int tmax = max(last0, max(has1 ? last1 + 1 : 0, has2 ? last2 + 2 : 0));
+            const int sl = s + (has2 ? 2 : (has1 ? 1 : 0));   // last sweep of the chain
+            double tau0 = 0.0, tau1 = 0.0, tau2 = 0.0;
             double pb[16], pd[16];   // sweep s, previous step
 #pragma unroll
             for (int q = 0; q < 16; ++q) { pb[q] = 0.0; pd[q] = 0.0; }
-            int tf = -1;            // last step of sweep s + 1 done
-            for (int t = 0;; ++t) {
-                const int lo = s + 1 + t * BW;
-                const bool lead = lo <= m - 1;
+            int tf = -1;             // steps of the last sweep stored and not yet published
+            for (int t = 0; t <= tmax; ++t) {
                 // lane-dependent indices are recomputed every step (not hoisted and
                 // kept live across the sweep loops)
                 int ln = lane;
                 asm volatile("" : "+v"(ln));
                 const int i = ln & 31, hh = ln >> 5;
                 const int csel = (((ln >> 4) & 1) << 3) | (((ln >> 3) & 1) << 2) | (((ln >> 2) & 1) << 1) | ((ln >> 1) & 1);
-                double cb[16], cd[16];   // sweep s, this step
-                double x = 0.0, betaL = 0.0;
-                const int L = lead ? min(BW, m - lo) : 0;
-                if (lead) {
+                // ---- step t of sweep s
+                double cb[16], cd[16];
+                double x = 0.0;
+                const bool run0 = t <= last0;
+                const int lo = s + 1 + t * BW;
+                if (run0) {
                     if (s > 0) {
                         const int need = (s - 1) * 4096 + min(t + 2, 4095);
                         while (__atomic_load_n(&prog[pw], __ATOMIC_RELAXED) < need) __builtin_amdgcn_s_sleep(1);
@@ -785,72 +847,75 @@ struct Band {
 #pragma unroll
                     for (int q = 0; q < 16; ++q) { cb[q] = 0.0; cd[q] = 0.0; }
                 }
-                // publish the steps of sweep s + 1 stored so far (they complete with these loads)
+                // publish the steps of the last sweep stored so far (they complete with these loads)
                 if (tf >= 0) {
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                    if (lane == 0) __atomic_store_n(&prog[wave], sf * 4096 + tf + 1, __ATOMIC_RELAXED);
+                    if (lane == 0) __atomic_store_n(&prog[wave], sl * 4096 + tf + 1, __ATOMIC_RELAXED);
+                    tf = -1;
                 }
-                if (lead) {
-                    betaL = chase_compute(t == 0, x, cb, cd, L, taupL, cvL, i, hh, csel);
-                    if (!pair) {
-                        chase_store(t == 0, s, lo, L, BW, betaL, cb, cd, i, hh);
-                    } else if (t == 0) {
-                        // column s and A(s + 1, s + 1) are final; the rest of this step
-                        // continues in sweep s + 1
-                        if (hh == 0 && i < L) bnd[(unsigned)(s * BLD + 1 + i)] = (i == 0) ? betaL : 0.0;
-                        if (lane == 0) bnd[(unsigned)(lo * BLD)] = cd[0];
+                if (run0) {
+                    const int L = min(BW, m - lo);
+                    const double beta = chase_compute(t == 0, x, cb, cd, L, tau0, cv0, i, hh, csel);
+                    if (!has1) {
+                        chase_store(t == 0, s, lo, L, BW, beta, cb, cd, i, hh);
+                        tf = t;
                     } else {
-                        // the annihilated first column of B below its first row is not part
-                        // of any block of sweep s + 1 (later sweeps read it as zero)
-                        if (hh == 0 && i >= 1 && i < L) bnd[(unsigned)((lo - BW) * BLD + BW + i)] = 0.0;
+                        chase_store_passing(t == 0, s, lo, L, beta, cd[0], i, hh);
                     }
                 }
                 // ---- step t - 1 of sweep s + 1, from steps t - 1 (pb, pd) and t (cb, cd) of sweep s
-                const int lof = s + 2 + (t - 1) * BW;
-                if (pair && t >= 1 && lof <= m - 1) {
-                    const int Lf = min(BW, m - lof);
-                    // first row of this step of sweep s (cols lo - 32 .. lo - 1) and its D(0, 0)
-                    if (i == 0) {
-#pragma unroll
-                        for (int q = 0; q < 16; ++q) row0[hh * 16 + q] = cb[q];
+                double fb[16], fd[16];
+                const int t1 = t - 1;
+                const bool run1 = has1 && t1 >= 0 && t1 <= last1;
+                if (run1) {
+                    const int lo1 = s + 2 + t1 * BW;
+                    const int L1 = min(BW, m - lo1);
+                    put_row0(row0a, cb, cd, i, hh);
+                    shift_blocks(pb, pd, row0a, fb, fd, i, hh);
+                    const bool first1 = (t1 == 0);
+                    const double x1 = from_upper(first1 ? fb[15] : 0.0);   // first step: column s + 1 is column 31
+                    const double beta1 = chase_compute(first1, x1, fb, fd, L1, tau1, cv1, i, hh, csel);
+                    if (!has2) {
+                        chase_store(first1, s + 1, lo1, L1, BW, beta1, fb, fd, i, hh);
+                        tf = t1;
+                    } else {
+                        chase_store_passing(first1, s + 1, lo1, L1, beta1, fd[0], i, hh);
                     }
-                    if (lane == 0) row0[BW] = cd[0];
-                    __builtin_amdgcn_wave_barrier();
-                    // shift left by one column.  Column 15 of the lower half takes column 16
-                    // from the upper half; column 31 takes D(i, 0) of the previous step (block
-                    // B) or the row just computed, row0[i] (block D; D is symmetric).
-                    const double sb = xswap32(pb[0], lane);   // lower half: B(i, 16)
-                    const double sd = xswap32(pd[0], lane);   // lower half: D(i, 16); upper half: D(i, 0)
-                    double fb[16], fd[16];
+                } else {
 #pragma unroll
-                    for (int q = 0; q < 15; ++q) { fb[q] = pb[q + 1]; fd[q] = pd[q + 1]; }
-                    fb[15] = hh ? sd : sb;
-                    fd[15] = hh ? row0[i] : sd;
-                    // shift up by one row; row 31 of B is zero but for its last column,
-                    // row 31 of D is the first row of this step of sweep s
+                    for (int q = 0; q < 16; ++q) { fb[q] = 0.0; fd[q] = 0.0; }
+                }
+                // ---- step t - 2 of sweep s + 2, from steps t - 2 (saved) and t - 1 (fb, fd) of sweep s + 1
+                if (has2) {
+                    const int t2 = t - 2;
+                    const bool run2 = t2 >= 0 && t2 <= last2;
+                    if (run2) put_row0(row0b, fb, fd, i, hh);
+                    // the saved blocks of step t - 2 of sweep s + 1 are read and this
+                    // step's blocks take their place, entry by entry (few live registers)
+                    double gb[16], gd[16];
 #pragma unroll
                     for (int q = 0; q < 16; ++q) {
-                        const double nb = dpp_mov<DPP_WAVE_SHL1>(fb[q]);   // lane + 1 (rows 31 replaced)
-                        const double nd = dpp_mov<DPP_WAVE_SHL1>(fd[q]);
-                        const int c = hh * 16 + q;
-                        fb[q] = (i < 31) ? nb : ((c == 31) ? row0[0] : 0.0);
-                        fd[q] = (i < 31) ? nd : row0[c + 1];
+                        gb[q] = saved[q * 64 + lane];
+                        gd[q] = saved[1024 + q * 64 + lane];
+                        if (run1) { saved[q * 64 + lane] = fb[q]; saved[1024 + q * 64 + lane] = fd[q]; }
                     }
-                    const bool ffirst = (t - 1 == 0);
-                    const double xf = ffirst ? fb[15] : 0.0;   // first step: column s + 1 is column 31
-                    const double xf0 = from_upper(xf);    // held by the upper half
-                    const double betaF = chase_compute(ffirst, xf0, fb, fd, Lf, taupF, cvF, i, hh, csel);
-                    chase_store(ffirst, sf, lof, Lf, BW, betaF, fb, fd, i, hh);
-                    tf = t - 1;
+                    if (run2) {
+                        const int lo2 = s + 3 + t2 * BW;
+                        const int L2 = min(BW, m - lo2);
+                        double hb[16], hd[16];
+                        shift_blocks(gb, gd, row0b, hb, hd, i, hh);
+                        const bool first2 = (t2 == 0);
+                        const double x2 = from_upper(first2 ? hb[15] : 0.0);
+                        const double beta2 = chase_compute(first2, x2, hb, hd, L2, tau2, cv2, i, hh, csel);
+                        chase_store(first2, s + 2, lo2, L2, BW, beta2, hb, hd, i, hh);
+                        tf = t2;
+                    }
                 }
-                // no later step of sweep s; then step t of sweep s + 1 would start at
-                // row lo + 1 > m - 1
-                if (!lead || L < 2) break;
 #pragma unroll
                 for (int q = 0; q < 16; ++q) { pb[q] = cb[q]; pd[q] = cd[q]; }
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            if (lane == 0) __atomic_store_n(&prog[wave], sf * 4096 + 4095, __ATOMIC_RELAXED);
+            if (lane == 0) __atomic_store_n(&prog[wave], sl * 4096 + 4095, __ATOMIC_RELAXED);
         }
         __syncthreads();
         for (int r = tid; r < m; r += NT) {
@@ -875,11 +940,21 @@ __host__ __device__ inline int64_t slot_bytes_band(int LDmax) {
     return ((tiles + 255) / 256) * 256 + panel + band + de;
 }
 
+// Doubles of the LDS region shared in turn by stage 1 (T, M, N, SYR2K
+// staging), the bulge chase (per-wave vectors, first rows and saved blocks,
+// then the progress counters) and the bisection (d, e^2).
+template <int NT>
+__host__ __device__ inline int64_t lds_big_band(int LDmax) {
+    constexpr int64_t nw = NT / 64;
+    const int64_t stage1 = 3 * BW * BW + 2 * BW * TILE;
+    const int64_t chase = nw * (6 * BW + 2 * 40 + 2 * 16 * 64) + (nw + 1) / 2;
+    const int64_t bis = 2 * (int64_t)LDmax;
+    return (stage1 > chase ? (stage1 > bis ? stage1 : bis) : (chase > bis ? chase : bis));
+}
+
 template <int NT>
 __host__ __device__ inline int64_t lds_bytes_band(int LDmax) {
-    const int64_t shared = 3 * BW * BW + 2 * BW * TILE;  // T, M, N, SYR2K staging; the bisection reuses it
-    const int64_t big = (shared > 2 * (int64_t)LDmax) ? shared : 2 * (int64_t)LDmax;
-    return (big + (NT / 64) * (2 * BW + 8) + 160) * 8 + 64;
+    return (lds_big_band<NT>(LDmax) + (NT / 64) * (2 * BW + 8) + 160) * 8 + 64;
 }
 
 template <class S, int NT>
@@ -893,8 +968,7 @@ void band_bisect_kernel(TriArgs args) {
     t.lane = threadIdx.x & 63;
     t.wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int LDmax = args.LDmax;
-    const int64_t shared = 3 * BW * BW + 2 * BW * TILE;
-    const int64_t big = (shared > 2 * (int64_t)LDmax) ? shared : 2 * (int64_t)LDmax;
+    const int64_t big = lds_big_band<NT>(LDmax);
     t.Tm = lds;
     t.Mm = lds + BW * BW;
     t.Nm = lds + 2 * BW * BW;
