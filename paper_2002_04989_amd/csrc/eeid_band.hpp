@@ -54,9 +54,9 @@ struct Band {
 
     S *tiles;
     double *V, *Wm, *bnd, *dg, *eg;    // slot
-    double *Tm, *Mm, *Nm, *stage;      // LDS: T, V^T X, T^T V^T X (BW x BW each), SYR2K staging
+    double *Tm, *Mm, *Nm;              // LDS: T, V^T X, T^T V^T X (BW x BW each); SYR2K staging from Tm on
     double *red, *vec;                 // LDS: per-wave partial sums, small vectors
-    double *de;                        // LDS: bisection (aliases Tm.. stage)
+    double *de;                        // LDS: bisection (aliases the stage-1 and chase region)
     int m, T, LD;
     int tid, lane, wave;
 
@@ -456,117 +456,93 @@ struct Band {
     }
 
     // ---------------------------------------------------------------- SYR2K
-    // C(I, J) -= V_I W_J^T + W_I V_J^T for tiles J >= J1, J-side rows staged in
-    // LDS per tile column (column k of the panel at vs[k*64 + row]).
-    __device__ void syr2k_tile(int I, const double *vs, const double *ws, int J, int sld) {
-        S *tp = tile_ptr(I, J);
-        const int lr = lane & 15, lk = lane >> 4;
-        const double *vI = V + I * TILE + lr, *wI = Wm + I * TILE + lr;
+    // C(I, J) -= V_I W_J^T + W_I V_J^T for tiles J >= J1, two tile columns at a
+    // time: their J-side rows are staged in LDS (tile column J + j at
+    // stg + j * 2 BW TILE, V then W, column k of the panel at [k * TILE + row]),
+    // and the I-side rows of each 32-row block are loaded once for the NJ tiles
+    // of the row.
+    template <int NJ>
+    __device__ void syr2k_rows(int I, int J, const double *stg) {
+        typedef typename std::conditional<sizeof(S) == 8, double, float>::type OpT;
+        typedef typename std::conditional<sizeof(S) == 8, dbl4, flt4>::type AccT;
 #pragma unroll 1
-        for (int ip = 0; ip < 4; ip += 2) {
-            if constexpr (sizeof(S) == 8) {
-                dbl4 acc[4][2];  // [jb][ib - ip]
+        for (int ib = 0; ib < 4; ++ib) {
+            // lane-dependent offsets are recomputed here (not hoisted out of the
+            // panel loop and kept live through the other phases)
+            int ln = lane;
+            asm volatile("" : "+v"(ln));
+            const int lr = ln & 15, lk = ln >> 4;
+            const double *vI = V + I * TILE + lr, *wI = Wm + I * TILE + lr;
+            // I-side operands of rows ib * 16 + lr, all K
+            OpT bv[BW / 4], bw[BW / 4];
+#pragma unroll
+            for (int kk = 0; kk < BW / 4; ++kk) {
+                const int64_t col = (int64_t)(4 * kk + lk) * LD + ib * 16;
+                bv[kk] = (OpT)vI[col];
+                bw[kk] = (OpT)wI[col];
+            }
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                S *tp = tile_ptr(I, J + j);
+                const double *vs = stg + j * 2 * BW * TILE, *ws = vs + BW * TILE;
+                AccT acc[4];
+#pragma unroll
+                for (int jb = 0; jb < 4; ++jb) acc[jb] = AccT{0, 0, 0, 0};
+#pragma unroll
+                for (int kk = 0; kk < BW / 4; ++kk) {
+                    const int sc = (4 * kk + lk) * TILE + lr;
+                    OpT aw[4], av[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) { aw[q] = (OpT)ws[sc + q * 16]; av[q] = (OpT)vs[sc + q * 16]; }
+#pragma unroll
+                    for (int jb = 0; jb < 4; ++jb) {
+                        if constexpr (sizeof(S) == 8) {
+                            acc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(aw[jb], bv[kk], acc[jb], 0, 0, 0);
+                            acc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[jb], bw[kk], acc[jb], 0, 0, 0);
+                        } else {
+                            acc[jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw[jb], bv[kk], acc[jb], 0, 0, 0);
+                            acc[jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[jb], bw[kk], acc[jb], 0, 0, 0);
+                        }
+                    }
+                }
+                // f64: acc[jb][g] = dC(row ib*16 + lr, col jb*16 + lk + 4g) (64 lanes x one
+                // register cover 512 contiguous bytes of the tile); f32: col jb*16 + 4 lk + g.
+                // All loads of the 16-row block are issued before its stores.
+                S c[4][4];
 #pragma unroll
                 for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
-                    for (int ib = 0; ib < 2; ++ib) acc[jb][ib] = dbl4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 2
-                for (int kk = 0; kk < BW; kk += 4) {
-                    const int64_t col = (int64_t)(kk + lk) * LD;
-                    const int64_t sc = (int64_t)(kk + lk) * sld + lr;
-                    double aw[4], av[4], bv[2], bw[2];
-#pragma unroll
-                    for (int q = 0; q < 2; ++q) { bv[q] = vI[col + (ip + q) * 16]; bw[q] = wI[col + (ip + q) * 16]; }
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) { aw[q] = ws[sc + q * 16]; av[q] = vs[sc + q * 16]; }
-#pragma unroll
-                    for (int jb = 0; jb < 4; ++jb)
-#pragma unroll
-                        for (int ib = 0; ib < 2; ++ib)
-                            acc[jb][ib] = __builtin_amdgcn_mfma_f64_16x16x4f64(aw[jb], bv[ib], acc[jb][ib], 0, 0, 0);
-#pragma unroll
-                    for (int jb = 0; jb < 4; ++jb)
-#pragma unroll
-                        for (int ib = 0; ib < 2; ++ib)
-                            acc[jb][ib] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[jb], bw[ib], acc[jb][ib], 0, 0, 0);
-                }
-                // acc[jb][ib][g] = dC(row (ip+ib)*16 + lr, col jb*16 + lk + 4g): 64 lanes x one
-                // register cover 512 contiguous bytes of the tile.  All loads of a
-                // 16-row block are issued before its stores.
-#pragma unroll
-                for (int ib = 0; ib < 2; ++ib) {
-                    S c[4][4];
-#pragma unroll
-                    for (int jb = 0; jb < 4; ++jb)
-#pragma unroll
-                        for (int g = 0; g < 4; ++g)
-                            c[jb][g] = __builtin_nontemporal_load(tp + mtile_off((ip + ib) * 16 + lr, jb * 16 + lk + 4 * g));
-#pragma unroll
-                    for (int jb = 0; jb < 4; ++jb)
-#pragma unroll
-                        for (int g = 0; g < 4; ++g)
-                            __builtin_nontemporal_store(c[jb][g] - acc[jb][ib][g],
-                                                        tp + mtile_off((ip + ib) * 16 + lr, jb * 16 + lk + 4 * g));
-                }
-            } else {
-                flt4 acc[4][2];
-#pragma unroll
-                for (int jb = 0; jb < 4; ++jb)
-#pragma unroll
-                    for (int ib = 0; ib < 2; ++ib) acc[jb][ib] = flt4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-                for (int kk = 0; kk < BW; kk += 4) {
-                    const int64_t col = (int64_t)(kk + lk) * LD;
-                    const int64_t sc = (int64_t)(kk + lk) * sld + lr;
-                    float aw[4], av[4], bv[2], bw[2];
-#pragma unroll
-                    for (int q = 0; q < 2; ++q) {
-                        bv[q] = (float)vI[col + (ip + q) * 16];
-                        bw[q] = (float)wI[col + (ip + q) * 16];
+                    for (int g = 0; g < 4; ++g) {
+                        const int cc = (sizeof(S) == 8) ? jb * 16 + lk + 4 * g : jb * 16 + 4 * lk + g;
+                        c[jb][g] = __builtin_nontemporal_load(tp + mtile_off(ib * 16 + lr, cc));
                     }
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) { aw[q] = (float)ws[sc + q * 16]; av[q] = (float)vs[sc + q * 16]; }
+                for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
-                    for (int jb = 0; jb < 4; ++jb)
-#pragma unroll
-                        for (int ib = 0; ib < 2; ++ib)
-                            acc[jb][ib] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw[jb], bv[ib], acc[jb][ib], 0, 0, 0);
-#pragma unroll
-                    for (int jb = 0; jb < 4; ++jb)
-#pragma unroll
-                        for (int ib = 0; ib < 2; ++ib)
-                            acc[jb][ib] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[jb], bw[ib], acc[jb][ib], 0, 0, 0);
-                }
-                // acc[jb][ib][g] = dC(row (ip+ib)*16 + lr, col jb*16 + 4 lk + g)
-#pragma unroll
-                for (int ib = 0; ib < 2; ++ib) {
-                    S c[4][4];
-#pragma unroll
-                    for (int jb = 0; jb < 4; ++jb)
-#pragma unroll
-                        for (int g = 0; g < 4; ++g)
-                            c[jb][g] = __builtin_nontemporal_load(tp + mtile_off((ip + ib) * 16 + lr, jb * 16 + 4 * lk + g));
-#pragma unroll
-                    for (int jb = 0; jb < 4; ++jb)
-#pragma unroll
-                        for (int g = 0; g < 4; ++g)
-                            __builtin_nontemporal_store(c[jb][g] - acc[jb][ib][g],
-                                                        tp + mtile_off((ip + ib) * 16 + lr, jb * 16 + 4 * lk + g));
-                }
+                    for (int g = 0; g < 4; ++g) {
+                        const int cc = (sizeof(S) == 8) ? jb * 16 + lk + 4 * g : jb * 16 + 4 * lk + g;
+                        __builtin_nontemporal_store(c[jb][g] - acc[jb][g], tp + mtile_off(ib * 16 + lr, cc));
+                    }
             }
         }
     }
 
     __device__ void syr2k(int J1) {
-        double *vs = stage, *ws = stage + BW * TILE;
-        for (int J = J1; J < T; ++J) {
-            for (int q = tid; q < BW * TILE; q += NT) {
-                const int kc = q / TILE, r = q % TILE;
-                vs[q] = V[(int64_t)kc * LD + J * TILE + r];
-                ws[q] = Wm[(int64_t)kc * LD + J * TILE + r];
+        double *stg = Tm;   // T, M and N are not needed again in this panel
+        for (int J = J1; J < T; J += 2) {
+            const int nj = min(2, T - J);
+            for (int q = tid; q < nj * BW * TILE; q += NT) {
+                const int j = q / (BW * TILE), qq = q % (BW * TILE);
+                const int kc = qq / TILE, r = qq % TILE;
+                stg[j * 2 * BW * TILE + qq] = V[(int64_t)kc * LD + (J + j) * TILE + r];
+                stg[j * 2 * BW * TILE + BW * TILE + qq] = Wm[(int64_t)kc * LD + (J + j) * TILE + r];
             }
             __syncthreads();
-            for (int I = J + wave; I < T; I += NWAVE) syr2k_tile(I, vs, ws, J, TILE);
+            // row J holds one tile of the pair (the other is above the diagonal)
+            for (int I = J + wave; I < T; I += NWAVE) {
+                if (I == J || nj == 1) syr2k_rows<1>(I, J, stg);
+                else syr2k_rows<2>(I, J, stg);
+            }
             __syncthreads();
         }
     }
@@ -946,7 +922,7 @@ __host__ __device__ inline int64_t slot_bytes_band(int LDmax) {
 template <int NT>
 __host__ __device__ inline int64_t lds_big_band(int LDmax) {
     constexpr int64_t nw = NT / 64;
-    const int64_t stage1 = 3 * BW * BW + 2 * BW * TILE;
+    const int64_t stage1 = 4 * BW * TILE;   // T, M, N (3 BW^2), then the SYR2K staging of two tile columns
     const int64_t chase = nw * (6 * BW + 2 * 40 + 2 * 16 * 64) + (nw + 1) / 2;
     const int64_t bis = 2 * (int64_t)LDmax;
     return (stage1 > chase ? (stage1 > bis ? stage1 : bis) : (chase > bis ? chase : bis));
@@ -972,7 +948,6 @@ void band_bisect_kernel(TriArgs args) {
     t.Tm = lds;
     t.Mm = lds + BW * BW;
     t.Nm = lds + 2 * BW * BW;
-    t.stage = lds + 3 * BW * BW;
     t.de = lds;
     t.red = lds + big;
     t.vec = t.red + (NT / 64) * (2 * BW + 8);
