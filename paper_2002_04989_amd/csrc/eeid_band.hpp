@@ -382,22 +382,47 @@ struct Band {
     // ------------------------------------------------------------ W from Y
     // X = Y T (rows >= r0), M = V^T X (matrix cores, LDS atomics), N = T^T M,
     // W = X - 1/2 V N; rows [J1*64, r0) of W are zero.
-    __device__ void make_w(int J1, int r0) {
-        for (int r = r0 + tid; r < LD; r += NT) {
-            double yr[BW];
+    // Rows [r0, LD) of Z = X2 - s * Y2 Q (in place in Wm when X2 = Wm), in
+    // 16-row blocks on matrix cores: Z^T = X2^T - s * Q^T Y2^T, with Q (BW x BW)
+    // in LDS (Q(k, n) at q[k * BW + n]).  For a block of rows rb..rb+15,
+    // operand a of lane l is Q^T(m, k) = Q(k, m), operand b is Y2(rb + l % 16, k),
+    // and result register g of lane l is Z^T(mb * 16 + l / 16 + 4 g, l % 16).
+    template <bool SUB>
+    __device__ void rows_times_small(int r0, const double *Y2, const double *q, double s) {
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
+        const int lr = ln & 15, lk = ln >> 4;
+        for (int rb = r0 + 16 * wave; rb < LD; rb += 16 * NWAVE) {
+            double bv[BW / 4];
 #pragma unroll
-            for (int l = 0; l < BW; ++l) yr[l] = Wm[(int64_t)l * LD + r];
-            __builtin_amdgcn_sched_barrier(0);
+            for (int kk = 0; kk < BW / 4; ++kk) bv[kk] = Y2[(int64_t)(4 * kk + lk) * LD + rb + lr];
+            dbl4 acc[2];
+            acc[0] = dbl4{0, 0, 0, 0};
+            acc[1] = dbl4{0, 0, 0, 0};
 #pragma unroll
-            for (int l = BW - 1; l >= 0; --l) {
-                double s = 0.0;
+            for (int kk = 0; kk < BW / 4; ++kk)
 #pragma unroll
-                for (int l2 = 0; l2 <= l; ++l2) s = fma(yr[l2], Tm[l2 * BW + l], s);
-                yr[l] = s;
+                for (int mb = 0; mb < 2; ++mb)
+                    acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(q[(4 * kk + lk) * BW + mb * 16 + lr], bv[kk], acc[mb], 0, 0, 0);
+            double xo[2][4];
+            if (SUB) {
+#pragma unroll
+                for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) xo[mb][g] = Wm[(int64_t)(mb * 16 + lk + 4 * g) * LD + rb + lr];
             }
 #pragma unroll
-            for (int l = 0; l < BW; ++l) Wm[(int64_t)l * LD + r] = yr[l];
+            for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                for (int g = 0; g < 4; ++g)
+                    Wm[(int64_t)(mb * 16 + lk + 4 * g) * LD + rb + lr] = SUB ? fma(-s, acc[mb][g], xo[mb][g]) : acc[mb][g];
         }
+    }
+
+    __device__ void make_w(int J1, int r0) {
+        // X = Y T (T upper triangular, its lower part zero in LDS); each block's Y
+        // is read before its X is written, by the same wave
+        rows_times_small<false>(r0, Wm, Tm, 0.0);
         for (int q = tid; q < BW * BW; q += NT) Mm[q] = 0.0;
         __syncthreads();
         {
@@ -435,24 +460,12 @@ struct Band {
             Nm[q] = s;
         }
         __syncthreads();
-        for (int r = J1 * TILE + tid; r < LD; r += NT) {
-            if (r < r0) {
-#pragma unroll
-                for (int l = 0; l < BW; ++l) Wm[(int64_t)l * LD + r] = 0.0;
-                continue;
-            }
-            double vr[BW], xr[BW];
-#pragma unroll
-            for (int l = 0; l < BW; ++l) { vr[l] = V[(int64_t)l * LD + r]; xr[l] = Wm[(int64_t)l * LD + r]; }
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int l = 0; l < BW; ++l) {
-                double s = 0.0;
-#pragma unroll
-                for (int l2 = 0; l2 < BW; ++l2) s = fma(vr[l2], Nm[l2 * BW + l], s);
-                Wm[(int64_t)l * LD + r] = fma(-0.5, s, xr[l]);
-            }
+        for (int q = tid; q < BW * (r0 - J1 * TILE); q += NT) {
+            const int l = q / (r0 - J1 * TILE), r = J1 * TILE + q % (r0 - J1 * TILE);
+            Wm[(int64_t)l * LD + r] = 0.0;
         }
+        // W = X - 1/2 V N
+        rows_times_small<true>(r0, V, Nm, 0.5);
     }
 
     // ---------------------------------------------------------------- SYR2K
