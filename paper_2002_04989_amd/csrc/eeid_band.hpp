@@ -474,8 +474,9 @@ struct Band {
     // stg + j * 2 BW TILE, V then W, column k of the panel at [k * TILE + row]),
     // and the I-side rows of each 32-row block are loaded once for the NJ tiles
     // of the row.
+    // 16-row blocks (FP64 trailing matrix)
     template <int NJ>
-    __device__ void syr2k_rows(int I, int J, const double *stg) {
+    __device__ void syr2k_rows16(int I, int J, const double *stg) {
         typedef typename std::conditional<sizeof(S) == 8, double, float>::type OpT;
         typedef typename std::conditional<sizeof(S) == 8, dbl4, flt4>::type AccT;
 #pragma unroll 1
@@ -538,6 +539,87 @@ struct Band {
                     }
             }
         }
+    }
+
+    // 32-row blocks (FP32 trailing matrix: its operands take half the registers)
+    template <int NJ>
+    __device__ void syr2k_rows32(int I, int J, const double *stg) {
+        typedef typename std::conditional<sizeof(S) == 8, double, float>::type OpT;
+        typedef typename std::conditional<sizeof(S) == 8, dbl4, flt4>::type AccT;
+#pragma unroll 1
+        for (int ip = 0; ip < 4; ip += 2) {
+            // lane-dependent offsets are recomputed here (not hoisted out of the
+            // panel loop and kept live through the other phases)
+            int ln = lane;
+            asm volatile("" : "+v"(ln));
+            const int lr = ln & 15, lk = ln >> 4;
+            const double *vI = V + I * TILE + lr, *wI = Wm + I * TILE + lr;
+            // I-side operands of rows (ip + q) * 16 + lr, all K
+            OpT bv[BW / 4][2], bw[BW / 4][2];
+#pragma unroll
+            for (int kk = 0; kk < BW / 4; ++kk) {
+                const int64_t col = (int64_t)(4 * kk + lk) * LD + ip * 16;
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    bv[kk][q] = (OpT)vI[col + q * 16];
+                    bw[kk][q] = (OpT)wI[col + q * 16];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                S *tp = tile_ptr(I, J + j);
+                const double *vs = stg + j * 2 * BW * TILE, *ws = vs + BW * TILE;
+                AccT acc[4][2];
+#pragma unroll
+                for (int jb = 0; jb < 4; ++jb) { acc[jb][0] = AccT{0, 0, 0, 0}; acc[jb][1] = AccT{0, 0, 0, 0}; }
+#pragma unroll
+                for (int kk = 0; kk < BW / 4; ++kk) {
+                    const int sc = (4 * kk + lk) * TILE + lr;
+                    OpT aw[4], av[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) { aw[q] = (OpT)ws[sc + q * 16]; av[q] = (OpT)vs[sc + q * 16]; }
+#pragma unroll
+                    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+                        for (int ib = 0; ib < 2; ++ib) {
+                            if constexpr (sizeof(S) == 8) {
+                                acc[jb][ib] = __builtin_amdgcn_mfma_f64_16x16x4f64(aw[jb], bv[kk][ib], acc[jb][ib], 0, 0, 0);
+                                acc[jb][ib] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[jb], bw[kk][ib], acc[jb][ib], 0, 0, 0);
+                            } else {
+                                acc[jb][ib] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw[jb], bv[kk][ib], acc[jb][ib], 0, 0, 0);
+                                acc[jb][ib] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[jb], bw[kk][ib], acc[jb][ib], 0, 0, 0);
+                            }
+                        }
+                }
+                // f64: acc[jb][ib][g] = dC(row (ip+ib)*16 + lr, col jb*16 + lk + 4g) (64 lanes x
+                // one register cover 512 contiguous bytes of the tile); f32: col jb*16 + 4 lk + g.
+                // All loads of a 16-row block are issued before its stores.
+#pragma unroll
+                for (int ib = 0; ib < 2; ++ib) {
+                    S c[4][4];
+#pragma unroll
+                    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+                        for (int g = 0; g < 4; ++g) {
+                            const int cc = (sizeof(S) == 8) ? jb * 16 + lk + 4 * g : jb * 16 + 4 * lk + g;
+                            c[jb][g] = __builtin_nontemporal_load(tp + mtile_off((ip + ib) * 16 + lr, cc));
+                        }
+#pragma unroll
+                    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+                        for (int g = 0; g < 4; ++g) {
+                            const int cc = (sizeof(S) == 8) ? jb * 16 + lk + 4 * g : jb * 16 + 4 * lk + g;
+                            __builtin_nontemporal_store(c[jb][g] - acc[jb][ib][g], tp + mtile_off((ip + ib) * 16 + lr, cc));
+                        }
+                }
+            }
+        }
+    }
+
+    template <int NJ>
+    __device__ void syr2k_rows(int I, int J, const double *stg) {
+        if constexpr (sizeof(S) == 8) syr2k_rows16<NJ>(I, J, stg);
+        else syr2k_rows32<NJ>(I, J, stg);
     }
 
     __device__ void syr2k(int J1) {
