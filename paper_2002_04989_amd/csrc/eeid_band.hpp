@@ -333,6 +333,80 @@ struct Band {
         }
     }
 
+    // FP32 trailing matrix: four consecutive rows of a micro-tile column come in
+    // one 16-byte load.  Column pass: lane l loads rows kq + 4 (l / 16) .. + 3 of
+    // column cb*16 + l % 16 and the same rows of V_I; the j-th MFMA of the four
+    // takes row kq + 4 (l / 16) + j as its K index.  acc as in the FP64 pass.
+    struct ColOps4 { flt4 a[4]; dpair b[2][2]; };   // a[cb]; b[jb][rows +0,+1 | +2,+3]
+    __device__ __forceinline__ void col_load4(ColOps4 &o, const S *tp, const double *vI, int kq) const {
+        const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+            o.a[cb] = __builtin_nontemporal_load(reinterpret_cast<const flt4 *>(tp + mtile_off(kq + 4 * lk, cb * 16 + lr)));
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+            for (int hf = 0; hf < 2; ++hf)
+                o.b[jb][hf] = *reinterpret_cast<const dpair *>(vI + (int64_t)(jb * 16 + lr) * LD + kq + 4 * lk + 2 * hf);
+    }
+    __device__ __forceinline__ void col_mfma4(const ColOps4 &o, dbl4 (&acc)[4][2]) const {
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[cb][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)o.a[cb][j], o.b[jb][j >> 1][j & 1],
+                                                                      acc[cb][jb], 0, 0, 0);
+    }
+    __device__ void symm_col_tile4(const S *tp, const double *vI, dbl4 (&acc)[4][2]) const {
+        ColOps4 o0, o1;
+        col_load4(o0, tp, vI, 0);
+#pragma unroll 1
+        for (int kq = 0; kq < TILE; kq += 32) {
+            col_load4(o1, tp, vI, kq + 16);
+            __builtin_amdgcn_sched_barrier(0);
+            col_mfma4(o0, acc);
+            if (kq + 32 < TILE) col_load4(o0, tp, vI, kq + 32);
+            __builtin_amdgcn_sched_barrier(0);
+            col_mfma4(o1, acc);
+        }
+    }
+    // Row pass: lane l loads rows 4 (l % 16) .. + 3 of column kq + l / 16;
+    // acc[x][jb] holds Y_I(4 i + x, jb*16 + j).
+    struct RowOps4 { flt4 a[2]; double b[2][2]; };   // a[kk]; b[kk][jb]
+    __device__ __forceinline__ void row_load4(RowOps4 &o, const S *tp, const double *vJ, int kq) const {
+        const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+            o.a[kk] = __builtin_nontemporal_load(reinterpret_cast<const flt4 *>(tp + mtile_off(4 * lr, kq + 4 * kk + lk)));
+#pragma unroll
+            for (int jb = 0; jb < 2; ++jb) o.b[kk][jb] = vJ[(int64_t)(jb * 16 + lr) * LD + kq + 4 * kk + lk];
+        }
+    }
+    __device__ __forceinline__ void row_mfma4(const RowOps4 &o, dbl4 (&acc)[4][2]) const {
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int jb = 0; jb < 2; ++jb)
+                    acc[x][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)o.a[kk][x], o.b[kk][jb], acc[x][jb], 0, 0, 0);
+    }
+    __device__ void symm_row_tile4(const S *tp, const double *vJ, dbl4 (&acc)[4][2]) const {
+        RowOps4 o0, o1;
+        row_load4(o0, tp, vJ, 0);
+#pragma unroll 1
+        for (int kq = 0; kq < TILE; kq += 16) {
+            row_load4(o1, tp, vJ, kq + 8);
+            __builtin_amdgcn_sched_barrier(0);
+            row_mfma4(o0, acc);
+            if (kq + 16 < TILE) row_load4(o0, tp, vJ, kq + 16);
+            __builtin_amdgcn_sched_barrier(0);
+            row_mfma4(o1, acc);
+        }
+    }
+
     // Y block of tile row/column K (64 x BW) from the accumulators: result
     // register g of lane l is D(l / 16 + 4 g, l % 16) of block acc[x][jb], which
     // is Y row `rowof(x, l / 16 + 4 g)` of the block, column jb*16 + l % 16.
@@ -362,7 +436,10 @@ struct Band {
             dbl4 acc[4][2];
 #pragma unroll
             for (int a = 0; a < 4; ++a) { acc[a][0] = dbl4{0, 0, 0, 0}; acc[a][1] = dbl4{0, 0, 0, 0}; }
-            for (int I = J + 1; I < T; ++I) symm_col_tile(tile_ptr(I, J), V + I * TILE, acc);
+            for (int I = J + 1; I < T; ++I) {
+                if constexpr (sizeof(S) == 4) symm_col_tile4(tile_ptr(I, J), V + I * TILE, acc);
+                else symm_col_tile(tile_ptr(I, J), V + I * TILE, acc);
+            }
             store_y(J, acc, false, [](int x, int i) { return x * 16 + i; });
         }
         __syncthreads();
@@ -374,8 +451,13 @@ struct Band {
             dbl4 acc[4][2];
 #pragma unroll
             for (int a = 0; a < 4; ++a) { acc[a][0] = dbl4{0, 0, 0, 0}; acc[a][1] = dbl4{0, 0, 0, 0}; }
-            for (int J = J1; J <= I; ++J) symm_row_tile(tile_ptr(I, J), V + J * TILE, acc);
-            store_y(I, acc, true, [](int x, int i) { return (x >> 1) * 32 + 2 * i + (x & 1); });
+            if constexpr (sizeof(S) == 4) {
+                for (int J = J1; J <= I; ++J) symm_row_tile4(tile_ptr(I, J), V + J * TILE, acc);
+                store_y(I, acc, true, [](int x, int i) { return 4 * i + x; });
+            } else {
+                for (int J = J1; J <= I; ++J) symm_row_tile(tile_ptr(I, J), V + J * TILE, acc);
+                store_y(I, acc, true, [](int x, int i) { return (x >> 1) * 32 + 2 * i + (x & 1); });
+            }
         }
     }
 
