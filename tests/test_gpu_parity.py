@@ -194,6 +194,62 @@ def test_every_real_kernel_configuration(variant):
         eeid.set_variant(None)
 
 
+class _OneSlot:
+    """A library handle with one resident problem: the items run one after
+    another, largest first, so each matrix finishes before its own minors."""
+
+    def __enter__(self):
+        import ctypes
+        import os
+        import torch
+        from paper_2002_04989_amd import eeid
+        self.eeid, self.lib = eeid, eeid.load_library()
+        self.dev = torch.cuda.current_device()
+        self.old = eeid._handles.get(self.dev)
+        os.environ["EEID_MAX_SLOTS"] = "1"
+        try:
+            hp = eeid._vp()
+            eeid._check(self.lib.eeid_create(ctypes.byref(hp), self.dev))
+        finally:
+            del os.environ["EEID_MAX_SLOTS"]
+        self.h = hp
+        eeid._handles[self.dev] = hp
+        return self
+
+    def __exit__(self, *exc):
+        import torch
+        torch.cuda.synchronize()
+        if self.old is None:
+            self.eeid._handles.pop(self.dev, None)
+        else:
+            self.eeid._handles[self.dev] = self.old
+        self.lib.eeid_destroy(self.h)
+        return False
+
+
+@pytest.mark.parametrize("variant", ["nb32_nt256x2", "band32_nt256x2", "complex"])
+def test_minors_bisected_from_interlacing_brackets(variant):
+    """With one resident problem each matrix's eigenvalues are final before its
+    minors are bisected, so every minor starts from the Cauchy-interlacing
+    brackets [lambda_k, lambda_k+1] (checked by Sturm counts) instead of the
+    Gershgorin interval: results must hold to the oracle's tolerances."""
+    from paper_2002_04989_amd import eeid
+    announce(f"interlacing brackets, one slot, {variant}")
+    if variant == "complex":
+        mats = [inputs.gue(33, 61), inputs.gue(65, 62)]
+    else:
+        mats = [inputs.goe(40, 63), inputs.goe(97, 64), inputs.wishart(70, 65)]
+    with _OneSlot():
+        if variant != "complex":
+            eeid.set_variant(variant)
+        try:
+            for A, got in zip(mats, run_all(mats, "fp64")):
+                check(A, got)
+        finally:
+            if variant != "complex":
+                eeid.set_variant(None)
+
+
 # ------------------------------------------------------------ complex Hermitian
 @pytest.mark.parametrize("n", [1, 2, 3, 17, 33, 64, 65, 100, 130])
 def test_gue_sizes(n):
