@@ -293,10 +293,11 @@ __device__ void bisect_tridiagonal(const double *dg, const double *eg, int m, do
                 const double d = de[2 * i], e2 = de[2 * i + 1];
 #pragma unroll
                 for (int t = 0; t < ILP; ++t) {
-                    // e2 / q by the hardware reciprocal and two Newton steps (a few ulp;
-                    // |q| >= pivmin keeps e2 / q finite)
+                    // e2 / q by the hardware reciprocal and one Newton step (at most 11
+                    // ulp over the double range; a relative error of that size in
+                    // e2 / q is a perturbation of e2 far below the reduction's
+                    // rounding; |q| >= pivmin keeps e2 / q finite)
                     double r = __builtin_amdgcn_rcp(q[t]);
-                    r = fma(fma(-q[t], r, 1.0), r, r);
                     r = fma(fma(-q[t], r, 1.0), r, r);
                     double v = (d - x[t]) - e2 * r;
                     v = (fabs(v) < pivmin) ? -pivmin : v;
