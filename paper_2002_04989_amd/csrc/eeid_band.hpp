@@ -109,6 +109,16 @@ struct Band {
     // of T and t = T^T V^T P(:,c+1) itself.  R goes to the band, v_c to V(:, c)
     // (written by the owner of each row at the start of the next pass), T to
     // LDS.
+    // sum over the wave of vr[l] * x for l < N, transposed: lane l ends with
+    // column l >> (6 - log2 N)
+    template <int N>
+    __device__ __forceinline__ double part_sum(const double (&vr)[BW], double x) const {
+        double w[N];
+#pragma unroll
+        for (int l = 0; l < N; ++l) w[l] = vr[l] * x;
+        return wave_transpose_sum<N>(w, lane);
+    }
+
     __device__ void panel_qr(int k0) {
         const int r0 = k0 + BW;
         double *zt = Nm + wave * 2 * BW;   // this wave's z = V^T P(:, c+1) and t = T^T z
@@ -172,17 +182,22 @@ struct Band {
                 const double xb = below ? xc : 0.0;
                 sig = fma(xb, xb, sig);
                 dx = fma(xb, xn, dx);
-                double wz[BW];
-#pragma unroll
-                for (int l = 0; l < BW; ++l) wz[l] = vr[l] * xn;       // V^T P(:, c+1), l < c
-                accq += wave_transpose_sum<BW>(wz, lane);
-#pragma unroll
-                for (int l = 0; l < BW; ++l) wz[l] = vr[l] * xb;       // V^T x_c(below), l < c
-                accg += wave_transpose_sum<BW>(wz, lane);
+                // V^T P(:, c+1) and V^T x_c(below): only columns l < c are nonzero, so
+                // the transpose-sum runs over 8, 16 or 32 of them (uniform choice)
+                if (c <= 8) {
+                    accq += part_sum<8>(vr, xn); accg += part_sum<8>(vr, xb);
+                } else if (c <= 16) {
+                    accq += part_sum<16>(vr, xn); accg += part_sum<16>(vr, xb);
+                } else {
+                    accq += part_sum<32>(vr, xn); accg += part_sum<32>(vr, xb);
+                }
             }
             sig = wave_sum(sig);
             dx = wave_sum(dx);
-            if ((lane & 1) == 0) { rd[wave * RED + (lane >> 1)] = accq; rd[wave * RED + BW + (lane >> 1)] = accg; }
+            {   // lane l holds column l >> (6 - log2 N) of the sums (columns >= N are not read)
+                const int sh = (c <= 8) ? 3 : ((c <= 16) ? 2 : 1);
+                if ((lane & ((1 << sh) - 1)) == 0) { rd[wave * RED + (lane >> sh)] = accq; rd[wave * RED + BW + (lane >> sh)] = accg; }
+            }
             if (lane == 0) { rd[wave * RED + 2 * BW] = sig; rd[wave * RED + 2 * BW + 1] = dx; }
             __syncthreads();
             // ---- every wave: reflector c, column c of T, t for column c + 1
