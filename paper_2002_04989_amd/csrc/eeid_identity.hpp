@@ -1,15 +1,19 @@
 // The eigenvector-eigenvalue identity (Section 2, Eq. (2) of the paper) for
 // every (i, j) of a batch, from the ascending spectra of A and of its minors:
 //
-//   |v_ij|^2 = exp( sum_k log|lambda_i - mu_jk| - sum_{k != i} log|lambda_i - lambda_k| )
+//   |v_ij|^2 = prod_k |lambda_i - mu_jk| / prod_{k != i} |lambda_i - lambda_k|
 //
 // in FP64.  Raw products over- and underflow for n of a few hundred (the paper
-// batches them for that reason, Section 3); the logarithms cannot.  Both sums
-// are Neumaier-compensated, and the denominator is kept as an unevaluated
-// (hi, lo) pair so that the difference of two sums of order n log||A|| keeps
-// its low-order bits.  An exactly zero numerator factor gives 0; an exactly
-// repeated lambda_i leaves the ratio undefined, so row i is NaN and the matrix
-// is flagged degenerate.
+// batches them for that reason, Section 3); here each product is carried as a
+// mantissa in [1/2, 1) and a separate integer exponent, renormalised after
+// every second factor.  The eigenvalues of a matrix are first scaled by 2^-E,
+// E the exponent of its largest |lambda| (exact, and the same for numerator
+// and denominator, which have n - 1 factors each), so every factor is below 4
+// and two of them can neither overflow nor leave the normal range.  The
+// rounding error is that of the n - 1 multiplications (relative, at most
+// about n eps).  An exactly zero numerator factor gives 0; an exactly repeated
+// lambda_i leaves the ratio undefined, so row i is NaN and the matrix is
+// flagged degenerate.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -24,12 +28,6 @@ struct BatchDesc {
     int32_t n;
     int32_t ncol;     // minors (columns) given: n for all of them, fewer for a subset
 };
-
-__device__ __forceinline__ void neumaier_add(double &s, double &c, double x) {
-    const double t = s + x;
-    c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
-    s = t;
-}
 
 __global__ __launch_bounds__(256) void prep_kernel(int32_t *flags, int64_t count, int *counter,
                                                    unsigned long long *lam_ready) {
@@ -73,6 +71,14 @@ __global__ __launch_bounds__(256) void nonfinite_kernel(const BatchDesc *desc, c
 }
 
 // Dpair[2 (lam_off + i) + {0, 1}] = (hi, lo) of sum_{k != i} log|lambda_i - lambda_k|.
+// Exponent of the largest |lambda| of an ascending spectrum (0 for an all-zero one).
+__device__ __forceinline__ int spectrum_exponent(const double *lam, int n) {
+    const double big = fmax(fabs(lam[0]), fabs(lam[n - 1]));
+    return (big > 0.0) ? ilogb(big) : 0;
+}
+
+// Denominator of Eq. (2) for each i: prod_{k != i} |lambda_i - lambda_k| 2^-E as
+// (mantissa, exponent) in Dpair[2 i], Dpair[2 i + 1].
 __global__ __launch_bounds__(256) void denominators_kernel(const BatchDesc *desc, const double *lambda,
                                                             double *Dpair, int32_t *flags) {
     const int b = blockIdx.y;
@@ -80,14 +86,18 @@ __global__ __launch_bounds__(256) void denominators_kernel(const BatchDesc *desc
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     const double *lam = lambda + desc[b].lam_off;
-    const double li = lam[i];
-    double s = 0.0, c = 0.0;
+    const int E = spectrum_exponent(lam, n);
+    const double li = ldexp(lam[i], -E);
+    double q = 1.0;
+    int qe = 0;
     bool zero = false;
     for (int k = 0; k < n; ++k) {
         if (k == i) continue;
-        const double d = li - lam[k];
+        const double d = li - ldexp(lam[k], -E);
         if (d == 0.0) zero = true;
-        else neumaier_add(s, c, log(fabs(d)));
+        int e;
+        q = frexp(q * fabs(d), &e);
+        qe += e;
     }
     double *out = Dpair + 2 * (desc[b].lam_off + i);
     if (zero) {
@@ -95,8 +105,8 @@ __global__ __launch_bounds__(256) void denominators_kernel(const BatchDesc *desc
         out[1] = 0.0;
         atomicOr(&flags[b], 2);
     } else {
-        out[0] = s;
-        out[1] = c;
+        out[0] = q;
+        out[1] = (double)qe;
     }
 }
 
@@ -116,43 +126,54 @@ __global__ __launch_bounds__(256) void identity_kernel(const BatchDesc *desc, co
     const int m = n - 1;
     const int i = blockIdx.x * 256 + threadIdx.x;
     const bool live = i < n;
-    const double li = live ? lambda[desc[b].lam_off + i] : 0.0;
+    const double *lam = lambda + desc[b].lam_off;
+    const int E = spectrum_exponent(lam, n);
+    const double li = live ? ldexp(lam[i], -E) : 0.0;
     const double *mub = mu + desc[b].mu_off;
-    double s[ID_JT], c[ID_JT];
-    bool zero[ID_JT];
+    double pm[ID_JT];
+    int pe[ID_JT];
 #pragma unroll
-    for (int t = 0; t < ID_JT; ++t) { s[t] = 0.0; c[t] = 0.0; zero[t] = false; }
+    for (int t = 0; t < ID_JT; ++t) { pm[t] = 1.0; pe[t] = 0; }
     for (int kc = 0; kc < m; kc += ID_KC) {
         const int kn = min(ID_KC, m - kc);
         __syncthreads();
+        // staged scaled by 2^-E
         for (int q = threadIdx.x; q < ID_JT * ID_KC; q += 256) {
             const int jj = q / ID_KC, kk = q % ID_KC;
             const int j = j0 + jj;
-            sm[jj][kk] = (j < ncol && kk < kn) ? mub[(int64_t)j * m + kc + kk] : 0.0;
+            sm[jj][kk] = (j < ncol && kk < kn) ? ldexp(mub[(int64_t)j * m + kc + kk], -E) : 0.0;
         }
         __syncthreads();
-        for (int kk = 0; kk < kn; ++kk) {
+        int kk = 0;
+        for (; kk + 1 < kn; kk += 2) {
 #pragma unroll
             for (int t = 0; t < ID_JT; ++t) {
-                const double d = li - sm[t][kk];
-                if (d == 0.0) zero[t] = true;
-                else neumaier_add(s[t], c[t], log(fabs(d)));
+                const double f = fabs(li - sm[t][kk]) * fabs(li - sm[t][kk + 1]);
+                int e;
+                pm[t] = frexp(pm[t] * f, &e);
+                pe[t] += e;
+            }
+        }
+        if (kk < kn) {
+#pragma unroll
+            for (int t = 0; t < ID_JT; ++t) {
+                int e;
+                pm[t] = frexp(pm[t] * fabs(li - sm[t][kk]), &e);
+                pe[t] += e;
             }
         }
     }
     if (!live) return;
     const double *dp = Dpair + 2 * (desc[b].lam_off + i);
-    const double dhi = dp[0], dlo = dp[1];
+    const double qm = dp[0];
+    const int qe = (int)dp[1];
     double *out = V2 + desc[b].v2_off + (int64_t)i * ncol;
 #pragma unroll
     for (int t = 0; t < ID_JT; ++t) {
         const int j = j0 + t;
         if (j >= ncol) break;
-        double w;
-        if (isnan(dhi)) w = __builtin_nan("");
-        else if (zero[t]) w = 0.0;
-        else w = exp((s[t] - dhi) + (c[t] - dlo));
-        out[j] = w;
+        // a zero numerator factor left pm = 0 (frexp keeps 0); a NaN denominator stays NaN
+        out[j] = ldexp(pm[t] / qm, pe[t] - qe);
     }
 }
 
