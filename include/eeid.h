@@ -14,7 +14,8 @@
  * the GPU: eeid_minor_eigvals computes lambda(A) and all lambda(M_j) of a batch
  * of matrices in one persistent launch (Householder tridiagonalisation +
  * Sturm bisection), and eeid_components evaluates the ratio for every (i, j)
- * as a sum of logarithms of |differences| in FP64.
+ * as products of |differences| in FP64 with a separate exponent (no over- or
+ * underflow at any n).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -133,9 +134,12 @@ eeid_status_t eeid_minor_eigvals_subset(eeid_handle_t h, eeid_dtype_t t, eeid_pr
                                         int64_t n, const void *A, int64_t nsel, const int64_t *js,
                                         double *lambda, double *mu_sel, int32_t *flag);
 
-/* The identity, Eq. (2): V2_b[i * n_b + j] = exp( sum_k log|lambda_i - mu_jk|
- * - sum_{k != i} log|lambda_i - lambda_k| ) for every matrix, evaluated in
- * FP64 with compensated sums.  An exactly zero numerator factor gives 0; an
+/* The identity, Eq. (2): V2_b[i * n_b + j] = prod_k |lambda_i - mu_jk|
+ * / prod_{k != i} |lambda_i - lambda_k| for every matrix, evaluated in FP64
+ * with each product carried as a mantissa and a separate integer exponent
+ * (relative rounding at most about n_b eps).  mu is expected to interlace
+ * lambda, as the spectra of the minors do (then every scaled factor is below
+ * 4 and no renormalisation step can overflow).  An exactly zero numerator factor gives 0; an
  * exactly repeated lambda_i gives a NaN row and sets EEID_FLAG_DEGENERATE in
  * flags[b] (other bits are kept, so pass the flags of eeid_minor_eigvals).
  *   lambda, mu  device, laid out as eeid_minor_eigvals writes them
