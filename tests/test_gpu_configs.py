@@ -17,6 +17,9 @@ at any size:
   W = (Q**2)^T on every element.
 * complex Hermitian n=4096 (C128 and C64 forms): lambda(A) and two minors
   against stored oracle values.
+* real n=4700 (both two-stage configurations): lambda(A) and two minors
+  against the oracle's LAPACK mode, and interlacing; at this order the
+  bisection's LDS region sets the kernel's LDS size.
 
 Tolerances, FP64 forms: eigenvalues 1e-10 ||A||_2, |v_ij|^2 1e-9 absolute.
 The oracle's own error on the clustered matrix (intra-cluster gap 1e-6) is
@@ -193,3 +196,36 @@ def test_gue4096_sampled_minors(form):
         dm = np.max(np.abs(mu - g["mu"])) / s
         print(f"gue4096 c64 form: max|dlam|/||A||={dl:.2e} max|dmu|/||A||={dm:.2e}")
         assert dl < bound and dm < bound
+
+
+@pytest.fixture(scope="module")
+def large_real():
+    n = 4700
+    A = inputs.goe(n, 47)
+    js = [0, 2351]
+    # LAPACK mode of the oracle (the Jacobi mode would take tens of minutes here)
+    return A, js, oracle.eigvalsh(A, "lapack"), oracle.minor_spectra(A, js, "lapack")
+
+
+@pytest.mark.parametrize("variant", ["band32_nt512", "band32_nt256x2"])
+def test_large_real_order(large_real, variant):
+    """n = 4700 (padded order 4736): the bisection's LDS region (two doubles per
+    row) is then larger than the chase's and sets the LDS size; lambda(A) and
+    two minors against the oracle, and Cauchy interlacing."""
+    import torch
+    from paper_2002_04989_amd import eeid
+    A, js, lam_o, mu_o = large_real
+    announce(f"real n={A.shape[0]} subset, {variant}")
+    eeid.set_variant(variant)
+    try:
+        lam, mu, flag = eeid.minor_eigvals_subset(torch.from_numpy(A).to("cuda:0"), js)
+        torch.cuda.synchronize()
+    finally:
+        eeid.set_variant(None)
+    lam, mu = lam.cpu().numpy(), mu.cpu().numpy()
+    s = float(np.max(np.abs(lam_o)))
+    assert int(flag.cpu()[0]) == 0
+    np.testing.assert_allclose(lam, lam_o, atol=LAM_TOL * s, rtol=0)
+    np.testing.assert_allclose(mu, mu_o, atol=LAM_TOL * s, rtol=0)
+    for row in mu:
+        assert np.all(lam[:-1] <= row + 1e-12 * s) and np.all(row <= lam[1:] + 1e-12 * s)
