@@ -141,6 +141,21 @@ def test_invalid_arguments_raise():
         eeid.minor_eigvals_subset(torch.eye(4, dtype=torch.float64, device="cuda"), [4])
 
 
+def test_orders_above_the_maximum_are_rejected():
+    """n above the supported maximum (8192 real, 4160 complex) is refused with
+    EEID_ERR_UNSUPPORTED before anything is enqueued."""
+    import torch
+    from paper_2002_04989_amd import eeid
+    announce("orders above the maximum")
+    for n, dt in ((8193, torch.float64), (4161, torch.complex128)):
+        A = torch.zeros((n, n), dtype=dt, device="cuda")
+        with pytest.raises(eeid.EEIDError) as e:
+            eeid.eigvalsh_batched(A)
+        assert e.value.status == 5
+        del A
+    torch.cuda.synchronize()
+
+
 def test_repeat_calls_agree_to_rounding():
     """Reruns differ only by the order of LDS atomic additions (a few ulp)."""
     announce("reproducibility")
