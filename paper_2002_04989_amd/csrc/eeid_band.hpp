@@ -885,7 +885,7 @@ struct Band {
 
     // Stores of a step of sweep `sw` at rows lo..: column sw (first step) or B,
     // and the lower triangle of D.
-    __device__ void chase_store(bool first, int sw, int lo, int L, int pL, double beta, const double (&bk)[16],
+    __device__ void chase_store(bool first, int sw, int lo, int L, double beta, const double (&bk)[16],
                                 const double (&dk)[16], int i, int hh) {
         if (first) {
             if (hh == 0 && i < L) bnd[(unsigned)(sw * BLD + 1 + i)] = (i == 0) ? beta : 0.0;
@@ -893,9 +893,9 @@ struct Band {
             double *pb = bnd + (unsigned)((lo - BW) * BLD + BW + i + (BLD - 1) * hh * 16);
 #pragma unroll
             for (int q = 0; q < 16; ++q)
-                if (i < L && hh * 16 + q < pL) pb[(BLD - 1) * q] = bk[q];
+                if (i < L) pb[(BLD - 1) * q] = bk[q];
         }
-        {   // (also for L = 1: in a pair the diagonal entry may come from the other sweep)
+        {   // (also for L = 1: in a chain the diagonal entry may come from another sweep)
             double *pd = bnd + (unsigned)(lo * BLD + i + (BLD - 1) * hh * 16);
 #pragma unroll
             for (int q = 0; q < 16; ++q)
@@ -1025,7 +1025,7 @@ struct Band {
                     const int L = min(BW, m - lo);
                     const double beta = chase_compute(t == 0, x, cb, cd, L, tau0, cv0, i, hh, csel);
                     if (!has1) {
-                        chase_store(t == 0, s, lo, L, BW, beta, cb, cd, i, hh);
+                        chase_store(t == 0, s, lo, L, beta, cb, cd, i, hh);
                         tf = t;
                     } else {
                         chase_store_passing(t == 0, s, lo, L, beta, cd[0], i, hh);
@@ -1044,7 +1044,7 @@ struct Band {
                     const double x1 = from_upper(first1 ? fb[15] : 0.0);   // first step: column s + 1 is column 31
                     const double beta1 = chase_compute(first1, x1, fb, fd, L1, tau1, cv1, i, hh, csel);
                     if (!has2) {
-                        chase_store(first1, s + 1, lo1, L1, BW, beta1, fb, fd, i, hh);
+                        chase_store(first1, s + 1, lo1, L1, beta1, fb, fd, i, hh);
                         tf = t1;
                     } else {
                         chase_store_passing(first1, s + 1, lo1, L1, beta1, fd[0], i, hh);
@@ -1075,7 +1075,7 @@ struct Band {
                         const bool first2 = (t2 == 0);
                         const double x2 = from_upper(first2 ? hb[15] : 0.0);
                         const double beta2 = chase_compute(first2, x2, hb, hd, L2, tau2, cv2, i, hh, csel);
-                        chase_store(first2, s + 2, lo2, L2, BW, beta2, hb, hd, i, hh);
+                        chase_store(first2, s + 2, lo2, L2, beta2, hb, hd, i, hh);
                         tf = t2;
                     }
                 }
