@@ -573,11 +573,11 @@ struct Band {
     // of the row.
     // 16-row blocks (FP64 trailing matrix)
     template <int NJ>
-    __device__ void syr2k_rows16(int I, int J, const double *stg) {
+    __device__ void syr2k_rows16(int I, int J, const double *stg, int ib0, int ibstep) {
         typedef typename std::conditional<sizeof(S) == 8, double, float>::type OpT;
         typedef typename std::conditional<sizeof(S) == 8, dbl4, flt4>::type AccT;
 #pragma unroll 1
-        for (int ib = 0; ib < 4; ++ib) {
+        for (int ib = ib0; ib < 4; ib += ibstep) {
             // lane-dependent offsets are recomputed here (not hoisted out of the
             // panel loop and kept live through the other phases)
             int ln = lane;
@@ -640,11 +640,11 @@ struct Band {
 
     // 32-row blocks (FP32 trailing matrix: its operands take half the registers)
     template <int NJ>
-    __device__ void syr2k_rows32(int I, int J, const double *stg) {
+    __device__ void syr2k_rows32(int I, int J, const double *stg, int ip0, int ipstep) {
         typedef typename std::conditional<sizeof(S) == 8, double, float>::type OpT;
         typedef typename std::conditional<sizeof(S) == 8, dbl4, flt4>::type AccT;
 #pragma unroll 1
-        for (int ip = 0; ip < 4; ip += 2) {
+        for (int ip = ip0; ip < 4; ip += ipstep) {
             // lane-dependent offsets are recomputed here (not hoisted out of the
             // panel loop and kept live through the other phases)
             int ln = lane;
@@ -713,10 +713,18 @@ struct Band {
         }
     }
 
+    // Blocks of tile row I dealt to this wave: the 16-row (FP64) or 32-row (FP32)
+    // blocks of every tile row are spread over the waves, so each wave gets the
+    // same number of blocks in every tile column pair (no wave waits for
+    // another's extra tile row at the barrier).
+    static constexpr int RB = (sizeof(S) == 8) ? 16 : 32;     // rows per block
+    static constexpr int BPR = TILE / RB;                     // blocks per tile row
+    static constexpr int RSTEP = (NWAVE >= BPR) ? NWAVE / BPR : 1;   // tile rows in flight
     template <int NJ>
     __device__ void syr2k_rows(int I, int J, const double *stg) {
-        if constexpr (sizeof(S) == 8) syr2k_rows16<NJ>(I, J, stg);
-        else syr2k_rows32<NJ>(I, J, stg);
+        const int b0 = (NWAVE >= BPR) ? wave % BPR : 0, bstep = (NWAVE >= BPR) ? BPR : 1;
+        if constexpr (sizeof(S) == 8) syr2k_rows16<NJ>(I, J, stg, b0, bstep);
+        else syr2k_rows32<NJ>(I, J, stg, 2 * b0, 2 * bstep);
     }
 
     __device__ void syr2k(int J1) {
@@ -731,7 +739,7 @@ struct Band {
             }
             __syncthreads();
             // row J holds one tile of the pair (the other is above the diagonal)
-            for (int I = J + wave; I < T; I += NWAVE) {
+            for (int I = J + wave / BPR; I < T; I += RSTEP) {
                 if (I == J || nj == 1) syr2k_rows<1>(I, J, stg);
                 else syr2k_rows<2>(I, J, stg);
             }
