@@ -638,9 +638,10 @@ struct Band {
         }
     }
 
-    // 32-row blocks (FP32 trailing matrix: its operands take half the registers)
+    // 32-row blocks (FP32 trailing matrix: its operands take half the registers);
+    // stg holds FP32 copies of the J-side rows of up to four tile columns
     template <int NJ>
-    __device__ void syr2k_rows32(int I, int J, const double *stg, int ip0, int ipstep) {
+    __device__ void syr2k_rows32(int I, int J, const float *stg, int ip0, int ipstep) {
         typedef typename std::conditional<sizeof(S) == 8, double, float>::type OpT;
         typedef typename std::conditional<sizeof(S) == 8, dbl4, flt4>::type AccT;
 #pragma unroll 1
@@ -665,7 +666,7 @@ struct Band {
 #pragma unroll
             for (int j = 0; j < NJ; ++j) {
                 S *tp = tile_ptr(I, J + j);
-                const double *vs = stg + j * 2 * BW * TILE, *ws = vs + BW * TILE;
+                const float *vs = stg + j * 2 * BW * TILE, *ws = vs + BW * TILE;
                 AccT acc[4][2];
 #pragma unroll
                 for (int jb = 0; jb < 4; ++jb) { acc[jb][0] = AccT{0, 0, 0, 0}; acc[jb][1] = AccT{0, 0, 0, 0}; }
@@ -720,30 +721,50 @@ struct Band {
     static constexpr int RB = (sizeof(S) == 8) ? 16 : 32;     // rows per block
     static constexpr int BPR = TILE / RB;                     // blocks per tile row
     static constexpr int RSTEP = (NWAVE >= BPR) ? NWAVE / BPR : 1;   // tile rows in flight
-    template <int NJ>
-    __device__ void syr2k_rows(int I, int J, const double *stg) {
-        const int b0 = (NWAVE >= BPR) ? wave % BPR : 0, bstep = (NWAVE >= BPR) ? BPR : 1;
-        if constexpr (sizeof(S) == 8) syr2k_rows16<NJ>(I, J, stg, b0, bstep);
-        else syr2k_rows32<NJ>(I, J, stg, 2 * b0, 2 * bstep);
-    }
+    static constexpr int B0STEP = (NWAVE >= BPR) ? BPR : 1;
+    __device__ int block0() const { return (NWAVE >= BPR) ? wave % BPR : 0; }
 
     __device__ void syr2k(int J1) {
-        double *stg = Tm;   // T, M and N are not needed again in this panel
-        for (int J = J1; J < T; J += 2) {
-            const int nj = min(2, T - J);
-            for (int q = tid; q < nj * BW * TILE; q += NT) {
-                const int j = q / (BW * TILE), qq = q % (BW * TILE);
-                const int kc = qq / TILE, r = qq % TILE;
-                stg[j * 2 * BW * TILE + qq] = V[(int64_t)kc * LD + (J + j) * TILE + r];
-                stg[j * 2 * BW * TILE + BW * TILE + qq] = Wm[(int64_t)kc * LD + (J + j) * TILE + r];
+        if constexpr (sizeof(S) == 8) {
+            double *stg = Tm;   // T, M and N are not needed again in this panel
+            for (int J = J1; J < T; J += 2) {
+                const int nj = min(2, T - J);
+                for (int q = tid; q < nj * BW * TILE; q += NT) {
+                    const int j = q / (BW * TILE), qq = q % (BW * TILE);
+                    const int kc = qq / TILE, r = qq % TILE;
+                    stg[j * 2 * BW * TILE + qq] = V[(int64_t)kc * LD + (J + j) * TILE + r];
+                    stg[j * 2 * BW * TILE + BW * TILE + qq] = Wm[(int64_t)kc * LD + (J + j) * TILE + r];
+                }
+                __syncthreads();
+                // row J holds one tile of the pair (the other is above the diagonal)
+                for (int I = J + wave / BPR; I < T; I += RSTEP) {
+                    if (I == J || nj == 1) syr2k_rows16<1>(I, J, stg, block0(), B0STEP);
+                    else syr2k_rows16<2>(I, J, stg, block0(), B0STEP);
+                }
+                __syncthreads();
             }
-            __syncthreads();
-            // row J holds one tile of the pair (the other is above the diagonal)
-            for (int I = J + wave / BPR; I < T; I += RSTEP) {
-                if (I == J || nj == 1) syr2k_rows<1>(I, J, stg);
-                else syr2k_rows<2>(I, J, stg);
+        } else {
+            // FP32 operands (the update's arithmetic is FP32): four tile columns fit
+            float *stg = reinterpret_cast<float *>(Tm);
+            for (int J = J1; J < T; J += 4) {
+                const int nj = min(4, T - J);
+                for (int q = tid; q < nj * BW * TILE; q += NT) {
+                    const int j = q / (BW * TILE), qq = q % (BW * TILE);
+                    const int kc = qq / TILE, r = qq % TILE;
+                    stg[j * 2 * BW * TILE + qq] = (float)V[(int64_t)kc * LD + (J + j) * TILE + r];
+                    stg[j * 2 * BW * TILE + BW * TILE + qq] = (float)Wm[(int64_t)kc * LD + (J + j) * TILE + r];
+                }
+                __syncthreads();
+                // row J + k holds k + 1 tiles of the group (the rest are above the diagonal)
+                for (int I = J + wave / BPR; I < T; I += RSTEP) {
+                    const int ntl = min(nj, I - J + 1);
+                    if (ntl == 1) syr2k_rows32<1>(I, J, stg, 2 * block0(), 2 * B0STEP);
+                    else if (ntl == 2) syr2k_rows32<2>(I, J, stg, 2 * block0(), 2 * B0STEP);
+                    else if (ntl == 3) syr2k_rows32<3>(I, J, stg, 2 * block0(), 2 * B0STEP);
+                    else syr2k_rows32<4>(I, J, stg, 2 * block0(), 2 * B0STEP);
+                }
+                __syncthreads();
             }
-            __syncthreads();
         }
     }
 
