@@ -566,11 +566,11 @@ struct Band {
     }
 
     // ---------------------------------------------------------------- SYR2K
-    // C(I, J) -= V_I W_J^T + W_I V_J^T for tiles J >= J1, two tile columns at a
-    // time: their J-side rows are staged in LDS (tile column J + j at
-    // stg + j * 2 BW TILE, V then W, column k of the panel at [k * TILE + row]),
-    // and the I-side rows of each 32-row block are loaded once for the NJ tiles
-    // of the row.
+    // C(I, J) -= V_I W_J^T + W_I V_J^T for tiles J >= J1, a group of tile
+    // columns at a time (two in FP64, four in FP32): their J-side rows are
+    // staged in LDS (tile column J + j at stg + j * 2 BW TILE, V then W, column
+    // k of the panel at [k * TILE + row]), and the I-side rows of each row
+    // block are loaded once for the NJ tiles of the row in the group.
     // 16-row blocks (FP64 trailing matrix)
     template <int NJ>
     __device__ void syr2k_rows16(int I, int J, const double *stg, int ib0, int ibstep) {
@@ -714,9 +714,9 @@ struct Band {
         }
     }
 
-    // Blocks of tile row I dealt to this wave: the 16-row (FP64) or 32-row (FP32)
-    // blocks of every tile row are spread over the waves, so each wave gets the
-    // same number of blocks in every tile column pair (no wave waits for
+    // Row blocks dealt to the waves: the 16-row (FP64) or 32-row (FP32) blocks
+    // of every tile row are spread over the waves, so each wave gets the same
+    // number of blocks in every group of tile columns (no wave waits for
     // another's extra tile row at the barrier).
     static constexpr int RB = (sizeof(S) == 8) ? 16 : 32;     // rows per block
     static constexpr int BPR = TILE / RB;                     // blocks per tile row
