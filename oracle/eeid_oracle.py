@@ -38,9 +38,11 @@ Readings of the paper taken here (the text is silent or garbled):
 * only the lower triangle of A is read and the imaginary parts of its
   diagonal are ignored.
 
-The EigenValues step is cyclic Jacobi in plain C (``jacobi.c``) by default.
-``method="lapack"`` swaps in ``numpy.linalg.eigvalsh`` as a library routine for
-the same step (used where Jacobi would take hours).
+The EigenValues step is cyclic Jacobi in plain C (``jacobi.c``), carried in
+extended precision by default (``method="jacobi"``; ``"jacobi64"`` runs the
+same code in double precision).  ``method="lapack"`` swaps in
+``numpy.linalg.eigvalsh`` as a library routine for the same step (used where
+Jacobi would take hours); it is a cross-check, not the oracle.
 """
 from __future__ import annotations
 
@@ -54,22 +56,22 @@ FLAG_NONFINITE_INPUT = 1
 FLAG_DEGENERATE = 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB = None
+_LIBS = {}
 
 
-def _lib():
-    global _LIB
-    if _LIB is None:
+def _lib(precision: str = "extended"):
+    lib = _LIBS.get(precision)
+    if lib is None:
         from . import build as _build
-        path = _build.build(force=False)
+        path = _build.build(force=False, precision=precision)
         lib = ctypes.CDLL(path)
         for name in ("oracle_jacobi_r64", "oracle_jacobi_c128"):
             f = getattr(lib, name)
             f.restype = ctypes.c_int
             f.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
-                          ctypes.c_void_p, ctypes.c_int]
-        _LIB = lib
-    return _LIB
+                          ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p]
+        _LIBS[precision] = lib
+    return lib
 
 
 def default_threads() -> int:
@@ -95,34 +97,71 @@ def hermitian_from_lower(a: np.ndarray) -> np.ndarray:
 # --------------------------------------------------------------------------
 # EigenValues(.) -- Algorithms 1 and 2, Section 3
 # --------------------------------------------------------------------------
-def eigh_jacobi(a: np.ndarray, vectors: bool = True, max_sweeps: int = 60):
-    """Jacobi eigen-decomposition: ascending w and (optionally) V with A V = V diag(w)."""
+def _jacobi_call(a, vectors, max_sweeps, precision, max_rounds=0):
     a = np.asarray(a)
     n = a.shape[0]
-    lib = _lib()
+    lib = _lib(precision)
     w = np.empty(n, dtype=np.float64)
+    st = np.zeros(2, dtype=np.int64)
     if np.iscomplexobj(a):
-        work = np.ascontiguousarray(a, dtype=np.complex128).copy()
+        work = np.ascontiguousarray(a, dtype=np.complex128)
         v = np.empty((n, n), dtype=np.complex128) if vectors else None
-        rc = lib.oracle_jacobi_c128(n, work.ctypes.data, w.ctypes.data,
-                                    v.ctypes.data if vectors else None, max_sweeps)
+        fn = lib.oracle_jacobi_c128
     else:
-        work = np.ascontiguousarray(a, dtype=np.float64).copy()
+        work = np.ascontiguousarray(a, dtype=np.float64)
         v = np.empty((n, n), dtype=np.float64) if vectors else None
-        rc = lib.oracle_jacobi_r64(n, work.ctypes.data, w.ctypes.data,
-                                   v.ctypes.data if vectors else None, max_sweeps)
+        fn = lib.oracle_jacobi_r64
+    rc = fn(n, work.ctypes.data, w.ctypes.data, v.ctypes.data if vectors else None, max_sweeps,
+            max_rounds, st.ctypes.data)
+    return rc, w, v, dict(sweeps=int(rc), rotations=int(st[0]), rounds=int(st[1]))
+
+
+def eigh_jacobi(a: np.ndarray, vectors: bool = True, max_sweeps: int = 60,
+                precision: str = "extended", stats: dict | None = None):
+    """Jacobi eigen-decomposition: ascending w and (optionally) V with A V = V diag(w).
+
+    ``precision`` is the working precision of the rotations: "extended" (x87,
+    64-bit significand; the default) or "double".  Input and output are FP64.
+    If ``stats`` is a dict it receives the sweeps, rotations and rounds taken.
+    """
+    rc, w, v, st = _jacobi_call(a, vectors, max_sweeps, precision)
     if rc < 0:
-        raise RuntimeError(f"Jacobi did not converge in {max_sweeps} sweeps (n={n})")
+        raise RuntimeError(f"Jacobi did not converge in {max_sweeps} sweeps (n={np.asarray(a).shape[0]})")
+    if stats is not None:
+        stats.update(st)
     return (w, v) if vectors else w
 
 
-def eigvalsh(a: np.ndarray, method: str = "jacobi") -> np.ndarray:
+def jacobi_rounds_sample(a: np.ndarray, max_rounds: int, precision: str = "extended") -> dict:
+    """Time the first ``max_rounds`` rounds of the Jacobi iteration on ``a``.
+
+    Only a timing aid for bounded samples of problems too large to finish
+    (the benchmark's CPU baseline): returns the wall seconds, rounds and
+    rotations of the capped run; its eigenvalue output is discarded.
+    """
+    import time
+    t0 = time.perf_counter()
+    rc, _, _, st = _jacobi_call(a, False, 60, precision, max_rounds=max_rounds)
+    st["seconds"] = time.perf_counter() - t0
+    st["capped"] = rc == -2
+    return st
+
+
+# EigenValues methods: "jacobi" (extended-precision Jacobi, the oracle),
+# "jacobi64" (the same code in double precision) and "lapack" (numpy's
+# eigvalsh, a library routine, not the oracle).
+METHODS = ("jacobi", "jacobi64", "lapack")
+
+
+def eigvalsh(a: np.ndarray, method: str = "jacobi", stats: dict | None = None) -> np.ndarray:
     """Ascending eigenvalues of the Hermitian matrix given by the lower triangle of ``a``."""
     a = np.asarray(a)
     if a.shape[0] == 0:
         return np.zeros(0)
     if method == "jacobi":
-        return eigh_jacobi(a, vectors=False)
+        return eigh_jacobi(a, vectors=False, precision="extended", stats=stats)
+    if method == "jacobi64":
+        return eigh_jacobi(a, vectors=False, precision="double", stats=stats)
     if method == "lapack":
         return np.linalg.eigvalsh(a, UPLO="L").astype(np.float64)
     raise ValueError(method)

@@ -59,17 +59,23 @@ def laplacian_closed(n):
     return lam, np.array(mu).reshape(n, n - 1), W
 
 
+@pytest.mark.parametrize("method", ["jacobi", "jacobi64"])
 @pytest.mark.parametrize("n", [1, 2, 3, 8, 64, 127])
-def test_laplacian_closed_form(n):
+def test_laplacian_closed_form(n, method):
     A = inputs.laplacian(n)
     lam_x, mu_x, W_x = laplacian_closed(n)
-    lam, mu, W, flags = oracle.components_identity(A)
+    lam, mu, W, flags = oracle.components_identity(A, method=method)
     assert flags == 0
-    tol = 1e-14 + 8e-15 * n          # backward error of Jacobi grows with the rotations applied
+    if method == "jacobi":
+        # extended-precision rotations: within a few ulp of the closed form at every n
+        tol, wtol = 2e-15, 2e-14
+    else:
+        # double-precision rotations: the backward error grows with the rotations applied
+        tol, wtol = 1e-14 + 8e-15 * n, 1e-11
     np.testing.assert_allclose(lam, lam_x, atol=tol, rtol=0)
     if n > 1:
         np.testing.assert_allclose(mu, mu_x, atol=tol, rtol=0)
-    np.testing.assert_allclose(W, W_x, atol=1e-11, rtol=0)
+    np.testing.assert_allclose(W, W_x, atol=wtol, rtol=0)
 
 
 def test_diagonal_sorted_gives_identity():
@@ -91,14 +97,15 @@ def test_diagonal_unsorted_gives_permutation():
 
 
 # ---------------------------------------------------------------- brute force
+@pytest.mark.parametrize("method", ["jacobi", "jacobi64"])
 @pytest.mark.parametrize("cplx", [False, True])
-def test_brute_force_tiny(cplx):
+def test_brute_force_tiny(cplx, method):
     """The method against the plain definition on many tiny random matrices."""
     worst = 0.0
     for seed in range(300):
         n = 1 + seed % 8
         A = inputs.gue(n, seed) if cplx else inputs.goe(n, seed)
-        lam, mu, W, flags = oracle.components_identity(A)
+        lam, mu, W, flags = oracle.components_identity(A, method=method)
         w_def, W_def = oracle.components_definition(A)
         assert flags == 0
         worst = max(worst, float(np.max(np.abs(W - W_def))))
@@ -125,14 +132,27 @@ def test_invariants(family):
     np.testing.assert_allclose(np.sum(lam ** 2), np.sum(np.abs(A) ** 2), rtol=1e-13)
 
 
-def test_clustered_known_eigenvectors():
-    """Q diag(lam) Q^T with tiny intra-cluster gaps: exact W is (Q**2)^T."""
-    A, lam_true, Q = inputs.clustered(192, clusters=3, gap=1e-6, seed=40)
-    lam, mu, W, flags = oracle.components_identity(A)
+@pytest.mark.parametrize("n,clusters,js,wtol", [
+    (192, 3, None, 5e-11),
+    (192, 16, None, 5e-11),
+    (512, 16, [0, 1, 100, 255, 511], 2e-11),
+])
+def test_clustered_known_eigenvectors(n, clusters, js, wtol):
+    """Q diag(lam) Q^T with 1e-6 intra-cluster gaps: the exact W is (Q**2)^T.
+
+    The eigenvalues must come out within 1e-14 of the exact ones (a few ulp of
+    values of order 1); W then carries only the perturbation that rounding A
+    to double moves the eigenvectors by (measured 1.9e-11 at n = 192 and
+    4.2e-12 at n = 512), far inside the 1e-9 a GPU result is held to.  The
+    same Jacobi in double precision misses these bounds (eigenvalue errors of
+    1e-13, W errors of 1e-9)."""
+    A, lam_true, Q = inputs.clustered(n, clusters=clusters, gap=1e-6, seed=40)
+    lam, mu, W, flags = oracle.components_identity(A, js=js)
     assert flags == 0
-    np.testing.assert_allclose(lam, lam_true, atol=1e-13)
-    err = np.max(np.abs(W - (Q ** 2).T))
-    assert err < 1e-8, err
+    np.testing.assert_allclose(lam, lam_true, atol=1e-14, rtol=0)
+    W_x = (Q ** 2).T if js is None else (Q ** 2).T[:, js]
+    err = np.max(np.abs(W - W_x))
+    assert err < wtol, err
 
 
 def test_degenerate_identity_matrix_flags_nan_rows():
@@ -163,11 +183,25 @@ def test_lower_triangle_is_read():
 
 
 # ---------------------------------------------------------------- library cross-checks
+@pytest.mark.parametrize("method", ["jacobi", "jacobi64"])
 @pytest.mark.parametrize("n", [5, 40, 160])
-def test_jacobi_matches_lapack(n):
+def test_jacobi_matches_lapack(n, method):
     for A in (inputs.goe(n, n), inputs.gue(n, n), inputs.wishart(n, n)):
-        w = oracle.eigvalsh(A)
+        w = oracle.eigvalsh(A, method)
         np.testing.assert_allclose(w, np.linalg.eigvalsh(A), atol=1e-13 * n * np.max(np.abs(w)))
+
+
+def test_jacobi_round_cap_and_statistics():
+    """The timing aid: a capped run stops after the requested rounds and reports
+    them; the rotations of a full run match its per-rotation extrapolation."""
+    A = inputs.goe(64, 7)
+    st = {}
+    oracle.eigvalsh(A, "jacobi", stats=st)
+    assert st["sweeps"] >= 2 and st["rounds"] == st["sweeps"] * 63
+    assert 0 < st["rotations"] <= st["rounds"] * 32
+    cap = oracle.jacobi_rounds_sample(A, 10)
+    assert cap["capped"] and cap["rounds"] == 10
+    assert cap["rotations"] == 10 * 32      # every pair of the first sweep rotates
 
 
 def test_neumaier_matches_exact_sum():
