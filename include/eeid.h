@@ -75,7 +75,11 @@ typedef enum { EEID_PREC_FP64 = 0, EEID_PREC_FP32_TRAILING = 1 } eeid_prec_t;
 
 enum {
     EEID_FLAG_NONFINITE_INPUT = 1, /* a NaN/Inf in the lower triangle: all outputs of b are NaN */
-    EEID_FLAG_DEGENERATE = 2       /* lambda_i(A) repeated exactly: row i of V2 is NaN (Eq. (2) is 0/0) */
+    EEID_FLAG_DEGENERATE = 2,      /* lambda_i(A) repeated exactly: row i of V2 is NaN (Eq. (2) is 0/0) */
+    EEID_FLAG_WAIT_TIMEOUT = 4     /* a bounded wait between the waves of a workgroup gave up (a library
+                                      fault, never expected): the outputs of b are invalid.  The polls
+                                      allowed (default 2^26) can be set by the environment variable
+                                      EEID_SPIN_LIMIT, read by eeid_create */
 };
 
 /* Largest matrix order the library accepts (LDS holds two FP64/complex
@@ -136,12 +140,13 @@ eeid_status_t eeid_minor_eigvals_subset(eeid_handle_t h, eeid_dtype_t t, eeid_pr
 
 /* The identity, Eq. (2): V2_b[i * n_b + j] = prod_k |lambda_i - mu_jk|
  * / prod_{k != i} |lambda_i - lambda_k| for every matrix, evaluated in FP64
- * with each product carried as a mantissa and a separate integer exponent
- * (relative rounding at most about n_b eps).  mu is expected to interlace
- * lambda, as the spectra of the minors do (then every scaled factor is below
- * 4 and no renormalisation step can overflow).  An exactly zero numerator factor gives 0; an
- * exactly repeated lambda_i gives a NaN row and sets EEID_FLAG_DEGENERATE in
- * flags[b] (other bits are kept, so pass the flags of eeid_minor_eigvals).
+ * with each product carried as a mantissa and a separate integer exponent,
+ * every factor split into its own mantissa and exponent first (relative
+ * rounding at most about n_b eps, for any finite spectra: factors may range
+ * from the smallest subnormal to the largest double).  An exactly zero
+ * numerator factor gives 0; an exactly repeated lambda_i gives a NaN row and
+ * sets EEID_FLAG_DEGENERATE in flags[b] (other bits are kept, so pass the
+ * flags of eeid_minor_eigvals).
  *   lambda, mu  device, laid out as eeid_minor_eigvals writes them
  *   V2          device [sum n_b^2] output */
 eeid_status_t eeid_components(eeid_handle_t h, int64_t count, const int64_t *n,

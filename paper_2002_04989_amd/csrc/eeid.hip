@@ -58,6 +58,7 @@ struct eeid_handle_s {
     int variant = -1;           // >= 0: real-kernel configuration when the tune table has no entry
     int forced_variant = -1;    // >= 0: use this configuration (autotuning, EEID_VARIANT)
     int64_t max_slots = 0;      // > 0: cap on resident problems (EEID_MAX_SLOTS)
+    unsigned spin_limit = 1u << 26;   // polls before a bounded inter-wave wait gives up (EEID_SPIN_LIMIT)
     uint64_t generation = 0;    // bumped whenever a buffer the kernels read is reallocated or rewritten
     // graph mode
     bool graph_mode = false;
@@ -293,6 +294,7 @@ eeid_status_t prepare_eigs(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64
     a.work = reinterpret_cast<char *>(h->work.p);
     a.slot_bytes = kc.slot;
     a.LDmax = LDmax;
+    a.spin_limit = h->spin_limit;
     const eeid::BatchDesc *desc = reinterpret_cast<const eeid::BatchDesc *>(h->desc.p);
     const unsigned nn_blocks = (unsigned)((nmax * nmax + 4095) / 4096);
     const int cplx = (t == EEID_C128) ? 1 : 0;
@@ -450,6 +452,7 @@ eeid_status_t eeid_create(eeid_handle_t *out, int hip_device) {
         if (v >= 0 && v < N_REAL_VARIANTS) h->forced_variant = v;
     }
     if (const char *e = getenv("EEID_MAX_SLOTS")) h->max_slots = atoll(e);
+    if (const char *e = getenv("EEID_SPIN_LIMIT")) h->spin_limit = (unsigned)strtoul(e, nullptr, 10);
     load_tune_table(h);
     if (hipSetDevice(hip_device) != hipSuccess ||
         hipDeviceGetAttribute(&h->cu_count, hipDeviceAttributeMultiprocessorCount, hip_device) != hipSuccess ||

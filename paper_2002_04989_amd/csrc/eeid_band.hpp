@@ -984,7 +984,10 @@ struct Band {
     // LDS doubles per wave: 3 vp + vc, wv, cs; two first rows; the saved blocks
     static constexpr int CHASE_PER_WAVE = 6 * BW + 2 * 40 + 2 * 16 * 64;
 
-    __device__ void band_to_tridiagonal(double *scratch) {
+    // spin_limit bounds every wait for the previous chain: a wave that polls
+    // that often without progress gives up waiting for the rest of the problem,
+    // sets FLAG_WAIT_TIMEOUT in *flag and runs on, so the kernel always ends.
+    __device__ void band_to_tridiagonal(double *scratch, unsigned spin_limit, int32_t *flag) {
         int *prog = reinterpret_cast<int *>(scratch + NWAVE * CHASE_PER_WAVE);
         if (tid < NWAVE) prog[tid] = (CHAIN * (tid - NWAVE) + CHAIN - 1) * 4096 + 4095;
         __syncthreads();
@@ -995,6 +998,7 @@ struct Band {
         double *row0b = row0a + 40;         // ... of sweep s + 1
         double *saved = row0b + 40;         // blocks of sweep s + 1 of the previous step: [q * 64 + lane], D at + 1024
         const int pw = (wave + NWAVE - 1) % NWAVE;
+        bool bail = false;       // wave-uniform: a wait gave up, do not wait again
         for (int s = CHAIN * wave; s + 2 < m; s += CHAIN * NWAVE) {
             const bool has1 = s + 3 < m, has2 = s + 4 < m;
             const int last0 = (m - 2 - s) / BW;
@@ -1020,9 +1024,14 @@ struct Band {
                 const bool run0 = t <= last0;
                 const int lo = s + 1 + t * BW;
                 if (run0) {
-                    if (s > 0) {
+                    if (s > 0 && !bail) {
                         const int need = (s - 1) * 4096 + min(t + 2, 4095);
-                        while (__atomic_load_n(&prog[pw], __ATOMIC_RELAXED) < need) __builtin_amdgcn_s_sleep(1);
+                        unsigned polls = 0;
+                        while (__atomic_load_n(&prog[pw], __ATOMIC_RELAXED) < need) {
+                            if (++polls > spin_limit) { bail = true; break; }
+                            __builtin_amdgcn_s_sleep(1);
+                        }
+                        if (bail && lane == 0) atomicOr(flag, FLAG_WAIT_TIMEOUT);
                         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
                     }
                     // all loads of the step at once; entries outside the matrix are
@@ -1199,7 +1208,7 @@ void band_bisect_kernel(TriArgs args) {
         __syncthreads();
         t.reduce_to_band();
         __syncthreads();
-        t.band_to_tridiagonal(t.Tm);
+        t.band_to_tridiagonal(t.Tm, args.spin_limit, &args.flags[it.b]);
         t.bisect(it.out, interlacing_bracket(args, it, &s_flag));
         publish_eigenvalues(args, it);
         __syncthreads();

@@ -5,15 +5,18 @@
 //
 // in FP64.  Raw products over- and underflow for n of a few hundred (the paper
 // batches them for that reason, Section 3); here each product is carried as a
-// mantissa in [1/2, 1) and a separate integer exponent, renormalised after
-// every second factor.  The eigenvalues of a matrix are first scaled by 2^-E,
-// E the exponent of its largest |lambda| (exact, and the same for numerator
-// and denominator, which have n - 1 factors each), so every factor is below 4
-// and two of them can neither overflow nor leave the normal range.  The
-// rounding error is that of the n - 1 multiplications (relative, at most
-// about n eps).  An exactly zero numerator factor gives 0; an exactly repeated
-// lambda_i leaves the ratio undefined, so row i is NaN and the matrix is
-// flagged degenerate.
+// mantissa and a separate integer exponent.  Every factor is split by frexp
+// into a mantissa in [1/2, 1) and its exponent before it is multiplied in, so
+// a factor may be as small as the smallest subnormal or as large as the
+// largest double without any intermediate leaving the normal range; the
+// running mantissa (at least 2^-8 after eight factors) is renormalised after
+// every eighth factor.  The eigenvalues are used unscaled unless the largest
+// |lambda| reaches 2^1021, where a difference could overflow: then all of
+// them are scaled by the same power of two (exact; numerator and denominator
+// have n - 1 factors each, so the scale cancels).  The rounding error is that
+// of the n - 1 multiplications (relative, at most about n eps).  An exactly
+// zero numerator factor gives 0; an exactly repeated lambda_i leaves the ratio
+// undefined, so row i is NaN and the matrix is flagged degenerate.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -70,15 +73,33 @@ __global__ __launch_bounds__(256) void nonfinite_kernel(const BatchDesc *desc, c
         atomicOr(&flags[b], 1);
 }
 
-// Dpair[2 (lam_off + i) + {0, 1}] = (hi, lo) of sum_{k != i} log|lambda_i - lambda_k|.
-// Exponent of the largest |lambda| of an ascending spectrum (0 for an all-zero one).
+// Power of two by which the eigenvalues of an ascending spectrum are divided
+// before differences are taken: 0 unless the largest |lambda| is at least
+// 2^1021, so that every difference stays finite.
 __device__ __forceinline__ int spectrum_exponent(const double *lam, int n) {
     const double big = fmax(fabs(lam[0]), fabs(lam[n - 1]));
-    return (big > 0.0) ? ilogb(big) : 0;
+    const int e = (big > 0.0) ? ilogb(big) : 0;
+    return (e >= 1021) ? e - 1020 : 0;
 }
 
-// Denominator of Eq. (2) for each i: prod_{k != i} |lambda_i - lambda_k| 2^-E as
-// (mantissa, exponent) in Dpair[2 i], Dpair[2 i + 1].
+// Running product of factors as (mantissa, exponent): each factor's own
+// mantissa and exponent are taken apart first, so no intermediate leaves the
+// normal range; the mantissa is renormalised by the caller every RENORM
+// factors.  A zero factor leaves the mantissa 0 for good.
+constexpr int RENORM = 8;
+__device__ __forceinline__ void mul_factor(double &pm, int &pe, double f) {
+    int e;
+    pm *= frexp(f, &e);
+    pe += e;
+}
+__device__ __forceinline__ void renormalise(double &pm, int &pe) {
+    int e;
+    pm = frexp(pm, &e);
+    pe += e;
+}
+
+// Denominator of Eq. (2) for each i: prod_{k != i} |lambda_i - lambda_k| 2^-(n-1)E
+// as (mantissa, exponent) in Dpair[2 i], Dpair[2 i + 1].
 __global__ __launch_bounds__(256) void denominators_kernel(const BatchDesc *desc, const double *lambda,
                                                             double *Dpair, int32_t *flags) {
     const int b = blockIdx.y;
@@ -89,16 +110,16 @@ __global__ __launch_bounds__(256) void denominators_kernel(const BatchDesc *desc
     const int E = spectrum_exponent(lam, n);
     const double li = ldexp(lam[i], -E);
     double q = 1.0;
-    int qe = 0;
+    int qe = 0, cnt = 0;
     bool zero = false;
     for (int k = 0; k < n; ++k) {
         if (k == i) continue;
         const double d = li - ldexp(lam[k], -E);
         if (d == 0.0) zero = true;
-        int e;
-        q = frexp(q * fabs(d), &e);
-        qe += e;
+        mul_factor(q, qe, fabs(d));
+        if (++cnt == RENORM) { renormalise(q, qe); cnt = 0; }
     }
+    renormalise(q, qe);
     double *out = Dpair + 2 * (desc[b].lam_off + i);
     if (zero) {
         out[0] = __builtin_nan("");
@@ -145,23 +166,20 @@ __global__ __launch_bounds__(256) void identity_kernel(const BatchDesc *desc, co
         }
         __syncthreads();
         int kk = 0;
-        for (; kk + 1 < kn; kk += 2) {
+        for (; kk + RENORM <= kn; kk += RENORM) {
 #pragma unroll
             for (int t = 0; t < ID_JT; ++t) {
-                const double f = fabs(li - sm[t][kk]) * fabs(li - sm[t][kk + 1]);
-                int e;
-                pm[t] = frexp(pm[t] * f, &e);
-                pe[t] += e;
-            }
-        }
-        if (kk < kn) {
 #pragma unroll
-            for (int t = 0; t < ID_JT; ++t) {
-                int e;
-                pm[t] = frexp(pm[t] * fabs(li - sm[t][kk]), &e);
-                pe[t] += e;
+                for (int u = 0; u < RENORM; ++u) mul_factor(pm[t], pe[t], fabs(li - sm[t][kk + u]));
+                renormalise(pm[t], pe[t]);
             }
         }
+        for (; kk < kn; ++kk) {
+#pragma unroll
+            for (int t = 0; t < ID_JT; ++t) mul_factor(pm[t], pe[t], fabs(li - sm[t][kk]));
+        }
+#pragma unroll
+        for (int t = 0; t < ID_JT; ++t) renormalise(pm[t], pe[t]);
     }
     if (!live) return;
     const double *dp = Dpair + 2 * (desc[b].lam_off + i);

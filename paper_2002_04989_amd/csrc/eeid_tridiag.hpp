@@ -837,14 +837,20 @@ struct TriArgs {
     const Item *items;
     int64_t n_items;
     int *counter;
-    const int32_t *flags;
+    int32_t *flags;
     char *work;
     int64_t slot_bytes;
     int LDmax;
     // per batch: address of the matrix's own eigenvalues once they are final,
     // else 0 (cleared before every launch)
     unsigned long long *lam_ready;
+    // polls after which a wave waiting for another wave of its workgroup gives
+    // up (bounded waits: the problem is then flagged, and the kernel still ends)
+    unsigned spin_limit;
 };
+
+// flags bit of a problem whose bounded inter-wave wait gave up (its outputs are invalid)
+constexpr int32_t FLAG_WAIT_TIMEOUT = 4;
 
 // Bracket source for the bisection of item `it`: the eigenvalues of its
 // matrix if it is a minor and they are already final (published by the

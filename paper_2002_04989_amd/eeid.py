@@ -18,6 +18,7 @@ R64, C128 = 0, 1
 PREC = {"fp64": 0, "fp32": 1}
 FLAG_NONFINITE_INPUT = 1
 FLAG_DEGENERATE = 2
+FLAG_WAIT_TIMEOUT = 4
 STATUS = {0: "EEID_OK", 1: "EEID_ERR_INVALID_ARG", 2: "EEID_ERR_NO_DEVICE", 3: "EEID_ERR_ALLOC",
           4: "EEID_ERR_HIP", 5: "EEID_ERR_UNSUPPORTED"}
 

@@ -5,7 +5,7 @@ sample of minors M_j and the corresponding columns W[:, j] of Eq. (2).  The
 full-size GPU tests compare the library against these on the same seeded
 inputs (regenerated from paper_2002_04989_amd.inputs, which is deterministic).
 
-    python tests/golden/make_golden.py [goe2048] [clustered2048] [gue4096]
+    python tests/golden/make_golden.py [--threads T] [goe2048] [clustered2048] [gue4096]
 
 The n = 2048 workloads use the extended-precision Jacobi (the default
 oracle; about 25 min per eigenvalue problem on one core): its eigenvalue
@@ -64,8 +64,8 @@ def cpu_model() -> str:
     return platform.processor()
 
 
-def make(names) -> None:
-    threads = oracle.default_threads()
+def make(names, threads: int = 0) -> None:
+    threads = threads or oracle.default_threads()
     jobs = {}
     tasks = []   # (cost, name, slot): slot -1 = lambda(A), else the index into js
     for name in names:
@@ -116,4 +116,10 @@ def write(name, job, threads) -> None:
 
 
 if __name__ == "__main__":
-    make(sys.argv[1:] or ["goe2048", "clustered2048", "gue4096"])
+    args = sys.argv[1:]
+    nthreads = 0
+    if "--threads" in args:
+        k = args.index("--threads")
+        nthreads = int(args[k + 1])
+        del args[k:k + 2]
+    make(args or ["goe2048", "clustered2048", "gue4096"], nthreads)

@@ -23,6 +23,7 @@ def run_all(mats, prec="fp64"):
     mu = eeid.split(mu.cpu().numpy(), n, "mu")
     W = eeid.split(V2.cpu().numpy(), n, "V2")
     flags = flags.cpu().numpy()
+    assert not np.any(flags & eeid.FLAG_WAIT_TIMEOUT), "a bounded wait gave up"
     return [(lam[b], mu[b], W[b], int(flags[b])) for b in range(len(mats))]
 
 

@@ -1,12 +1,18 @@
 """CPU model of the identity kernel's arithmetic (design check; not the oracle).
 
 The GPU kernel evaluates Eq. (2) as two products, each carried as a mantissa
-in [1/2, 1) and a separate integer exponent: the eigenvalues of the matrix are
-first scaled by 2^-E (E the exponent of the largest |lambda|; exact), every
-second factor the mantissa is renormalised with frexp, and
-W = ldexp(P / Q, e_P - e_Q).  This model performs the same steps in numpy and
-checks them against the oracle's compensated log sums (an independent
-formulation), and at scales where plain products overflow or underflow.
+and a separate integer exponent.  Every factor |lambda_i - x| is split by
+frexp into a mantissa in [1/2, 1) and an exponent before it is multiplied in;
+the running mantissa is renormalised after every eighth factor (the numerator
+also at the end of every LDS chunk of 256 minor eigenvalues, the denominator
+at its end), and W = ldexp(P / Q, e_P - e_Q).  The eigenvalues are scaled by
+a power of two only when the largest |lambda| reaches 2^1021.
+
+This model performs the same IEEE operations in the same order, so it gives
+the kernel's results bit for bit; the tests check it against the oracle's
+compensated log sums (an independent formulation), at scales where plain
+products overflow or underflow, and on graded spectra whose single factors
+lie far outside the range where a product of two of them stays normal.
 """
 import math
 
@@ -15,42 +21,75 @@ import pytest
 
 import oracle
 
+RENORM = 8
+KC = 256
 
-def scaled_product(factors):
-    """Product of the factors (each < 4) as (mantissa, exponent), renormalised
-    after every second factor, as the kernel does."""
-    m, e = 1.0, 0
-    k = 0
-    while k + 1 < len(factors):
-        m, de = math.frexp(m * (factors[k] * factors[k + 1]))
-        e += de
-        k += 2
-    if k < len(factors):
-        m, de = math.frexp(m * factors[k])
-        e += de
-    return m, e
+
+def spectrum_exponent(lam) -> int:
+    big = max(abs(lam[0]), abs(lam[-1]))
+    e = math.frexp(big)[1] - 1 if big > 0 else 0          # ilogb
+    return e - 1020 if e >= 1021 else 0
+
+
+def mul_factor(pm, pe, f):
+    fm, fe = math.frexp(f)
+    return pm * fm, pe + fe
+
+
+def renormalise(pm, pe):
+    m, e = math.frexp(pm)
+    return m, pe + e
+
+
+def denominator(ls, i):
+    q, qe, cnt = 1.0, 0, 0
+    zero = False
+    for k in range(len(ls)):
+        if k == i:
+            continue
+        d = ls[i] - ls[k]
+        zero = zero or d == 0.0
+        q, qe = mul_factor(q, qe, abs(d))
+        cnt += 1
+        if cnt == RENORM:
+            q, qe = renormalise(q, qe)
+            cnt = 0
+    q, qe = renormalise(q, qe)
+    return (math.nan, 0) if zero else (q, qe)
+
+
+def numerator(li, mus):
+    pm, pe = 1.0, 0
+    for kc in range(0, len(mus), KC):
+        chunk = mus[kc:kc + KC]
+        kk = 0
+        while kk + RENORM <= len(chunk):
+            for u in range(RENORM):
+                pm, pe = mul_factor(pm, pe, abs(li - chunk[kk + u]))
+            pm, pe = renormalise(pm, pe)
+            kk += RENORM
+        for u in range(kk, len(chunk)):
+            pm, pe = mul_factor(pm, pe, abs(li - chunk[u]))
+        pm, pe = renormalise(pm, pe)
+    return pm, pe
 
 
 def identity_model(lam, mu_rows):
+    """W[i, t] for the minor spectra mu_rows[t], step by step as the kernel."""
     lam = np.asarray(lam, dtype=np.float64)
     n = lam.shape[0]
-    big = max(abs(lam[0]), abs(lam[-1]))
-    E = math.frexp(big)[1] - 1 if big > 0 else 0          # exponent of the largest |lambda|
-    ls = np.ldexp(lam, -E)
+    E = spectrum_exponent(lam)
+    ls = [math.ldexp(float(x), -E) for x in lam]
     W = np.empty((n, len(mu_rows)))
     for i in range(n):
-        qf = [abs(ls[i] - ls[k]) for k in range(n) if k != i]
-        if any(f == 0.0 for f in qf):
-            W[i, :] = np.nan
-            continue
-        qm, qe = scaled_product(qf)
+        qm, qe = denominator(ls, i)
         for t, mu in enumerate(mu_rows):
-            pm, pe = scaled_product([abs(ls[i] - v) for v in np.ldexp(np.asarray(mu), -E)])
-            W[i, t] = math.ldexp(pm / qm, pe - qe)
+            pm, pe = numerator(ls[i], [math.ldexp(float(v), -E) for v in mu])
+            W[i, t] = math.ldexp(pm / qm, pe - qe) if not math.isnan(qm) else math.nan
     return W
 
 
-@pytest.mark.parametrize("n, seed", [(2, 1), (17, 2), (64, 3), (150, 4)])
+@pytest.mark.parametrize("n, seed", [(2, 1), (17, 2), (64, 3), (150, 4), (300, 6)])
 def test_model_matches_the_oracles_log_sums(n, seed):
     a = np.random.default_rng(seed).standard_normal((n, n))
     a = (a + a.T) / np.sqrt(2)
@@ -62,15 +101,19 @@ def test_model_matches_the_oracles_log_sums(n, seed):
     assert np.max(np.abs(W - W_log)) < 1e-13 * max(1, n / 16)
 
 
-@pytest.mark.parametrize("scale", [1e-250, 1e250])
+@pytest.mark.parametrize("scale", [1e-250, 1e250, 2.0 ** 1022])
 def test_model_at_scales_where_plain_products_fail(scale):
     # n = 300: the plain product of |differences| overflows (or underflows) in
-    # FP64 at these scales; the components are invariant under scaling of A
+    # FP64 at these scales; the components are invariant under scaling of A.
+    # At 2^1022 the eigenvalues themselves are near the top of the range and
+    # are scaled down before differences are taken.
     n = 300
     a = np.random.default_rng(5).standard_normal((n, n))
     a = (a + a.T) / np.sqrt(2)
     lam = oracle.eigvalsh(a, "lapack")
     mu = oracle.minor_spectra(a, [0, 150], "lapack")
+    lam = lam / np.max(np.abs(lam))
+    mu = mu / np.max(np.abs(oracle.eigvalsh(a, "lapack")))
     with np.errstate(over="ignore", under="ignore"):
         plain = np.prod(np.abs(lam[1:] * scale - lam[0] * scale))
     assert plain == 0.0 or not np.isfinite(plain)
@@ -78,6 +121,65 @@ def test_model_at_scales_where_plain_products_fail(scale):
     W = identity_model(lam * scale, mu * scale)
     assert np.all(np.isfinite(W))
     assert np.max(np.abs(W - W_ref)) < 1e-12
+
+
+@pytest.mark.parametrize("g", [1e-150, 1e-158, 1e-160, 1e-165, 1e-200, 1e-300, 5e-320])
+def test_graded_diagonal_gives_the_identity(g):
+    # diag(g, 2g, 3g, 1): W = I exactly.  Single factors are of order g, so a
+    # product of two of them leaves the normal range from g ~ 1e-154 on (and
+    # at 5e-320 every factor is itself subnormal).
+    a = np.diag([g, 2 * g, 3 * g, 1.0])
+    lam, mu, W_o, flags = oracle.components_identity(a)
+    assert flags == 0
+    W = identity_model(lam, mu)
+    np.testing.assert_array_equal(W, np.eye(4))
+    np.testing.assert_allclose(W_o, np.eye(4), atol=1e-15)
+
+
+def graded_block_spectra(k: int, seed: int = 11):
+    """Spectra of A = blockdiag(2^-k B, C) (B 5x5, C 6x6 GOE) and of all its
+    minors, assembled from those of B, C and their minors at unit scale (the
+    power-of-two scale is exact), with the components Eq. (2) must give: the
+    rows of the scaled eigenvalues hold B's components on B's indices and 0
+    elsewhere, the rows of C's eigenvalues C's components.
+
+    Returns (lam, mu, W_expected) with mu[j] the ascending spectrum of M_j.
+    """
+    r = np.random.default_rng(seed)
+    b = r.standard_normal((5, 5)); b = (b + b.T) / 2
+    c = r.standard_normal((6, 6)); c = (c + c.T) / 2
+    g = 2.0 ** -k
+    lb, mb, Wb, _ = oracle.components_identity(b)
+    lc, mc, Wc, _ = oracle.components_identity(c)
+    lam_parts = [(g * lb, 0), (lc, 1)]
+    lam = np.concatenate([p for p, _ in lam_parts])
+    order = np.argsort(lam, kind="stable")
+    lam = lam[order]
+    mu = np.empty((11, 10))
+    for j in range(11):
+        if j < 5:
+            mu[j] = np.sort(np.concatenate([g * mb[j], lc]))
+        else:
+            mu[j] = np.sort(np.concatenate([g * lb, mc[j - 5]]))
+    W = np.zeros((11, 11))
+    W[:5, :5] = Wb
+    W[5:, 5:] = Wc
+    return lam, mu, W[order]
+
+
+@pytest.mark.parametrize("k", [332, 531, 830, 1020])
+def test_graded_blocks_reduce_to_the_blocks(k):
+    # scales 2^-332 ~ 1e-100 ... 2^-1020 ~ 1e-307: the rows of the tiny
+    # eigenvalues have numerator and denominator factors of order 2^-k, whose
+    # pairwise products leave the normal range; the model and the oracle's
+    # log sums must both reproduce B's components computed at unit scale
+    lam, mu, W_exp = graded_block_spectra(k)
+    W = identity_model(lam, mu)
+    W_o, flags = oracle.identity_from_spectra(lam, mu)
+    assert flags == 0
+    assert np.max(np.abs(W - W_exp)) < 1e-13
+    # each logarithm is of order k ln 2 and carries a rounding error of eps times that
+    assert np.max(np.abs(W_o - W_exp)) < 10 * 11 * 2.3e-16 * k * math.log(2)
 
 
 def test_model_zero_factor_and_degenerate_row():
