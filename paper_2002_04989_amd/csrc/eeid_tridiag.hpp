@@ -293,13 +293,11 @@ __device__ void bisect_tridiagonal(const double *dg, const double *eg, int m, do
                 const double d = de[2 * i], e2 = de[2 * i + 1];
 #pragma unroll
                 for (int t = 0; t < ILP; ++t) {
-                    // e2 / q by the hardware reciprocal and one Newton step (at most 11
-                    // ulp over the double range; a relative error of that size in
-                    // e2 / q is a perturbation of e2 far below the reduction's
-                    // rounding; |q| >= pivmin keeps e2 / q finite)
-                    double r = __builtin_amdgcn_rcp(q[t]);
-                    r = fma(fma(-q[t], r, 1.0), r, r);
-                    double v = (d - x[t]) - e2 * r;
+                    // correctly rounded division: with monotone (correctly rounded)
+                    // arithmetic the count is monotone in x, which bisection relies
+                    // on; a reciprocal off by a few ulp breaks that within a few ulp
+                    // of an eigenvalue.  |q| >= pivmin keeps e2 / q finite.
+                    double v = (d - x[t]) - e2 / q[t];
                     v = (fabs(v) < pivmin) ? -pivmin : v;
                     cnt[t] += (v < 0.0) ? 1 : 0;
                     q[t] = v;
