@@ -153,6 +153,25 @@ eeid_status_t eeid_components(eeid_handle_t h, int64_t count, const int64_t *n,
                               const double *lambda, const double *mu, double *V2,
                               int32_t *flags);
 
+/* eeid_components for callers that cannot allocate device memory (code under
+ * hipGraph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and results, with the library's scratch (the batch
+ * descriptors and the denominator pairs) in a fixed device array of
+ * EEID_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends, instead of
+ * workspace it allocates.  The call allocates and frees nothing and copies
+ * nothing from the host; it only launches kernels on the handle's stream.
+ * Limits: count <= EEID_NOALLOC_MAX_MATRICES and sum n_b <=
+ * EEID_NOALLOC_MAX_EIGENVALUES, else EEID_ERR_UNSUPPORTED (nothing enqueued).
+ * Every call on one GPU shares that GPU's scratch: calls that overlap on one
+ * GPU (other streams, other handles or threads) race and must be ordered by
+ * the caller.  Arguments as for eeid_components. */
+#define EEID_NOALLOC_MAX_MATRICES 64
+#define EEID_NOALLOC_MAX_EIGENVALUES 16384
+#define EEID_NOALLOC_SCRATCH_BYTES (4096 + 16 * EEID_NOALLOC_MAX_EIGENVALUES)
+eeid_status_t eeid_components_noalloc(eeid_handle_t h, int64_t count, const int64_t *n,
+                                      const double *lambda, const double *mu, double *V2,
+                                      int32_t *flags);
+
 /* Columns of Eq. (2) for a subset of minors of ONE matrix of order n: the
  * squared components j_s of every eigenvector, from lambda(A) and the spectra
  * of the chosen minors (as eeid_minor_eigvals_subset writes them).  With one

@@ -44,6 +44,19 @@ constexpr int N_REAL_VARIANTS = 5;
 const char *const VARIANT_NAME[N_REAL_VARIANTS] = {"nb32_nt512", "nb32_nt256x2", "nb16_nt512", "band32_nt512",
                                                    "band32_nt256x2"};
 
+// Device scratch of eeid_components_noalloc: the batch descriptors, then the
+// (mantissa, exponent) pairs of the denominators.  Every GPU the library runs
+// on holds its own copy until the process ends; host code never uses this
+// name as an address (it is a host-side stand-in), only the per-device
+// address that hipGetSymbolAddress returns.
+constexpr size_t NOALLOC_DESC_BYTES = 4096;
+constexpr int64_t NOALLOC_MAX_EIGENVALUES = 16384;   // sum of n_b per call
+constexpr size_t NOALLOC_SCRATCH_BYTES = NOALLOC_DESC_BYTES + 2 * sizeof(double) * NOALLOC_MAX_EIGENVALUES;
+static_assert(eeid::NLIST_MAX * sizeof(eeid::BatchDesc) <= NOALLOC_DESC_BYTES, "descriptor region");
+static_assert(NOALLOC_MAX_EIGENVALUES == EEID_NOALLOC_MAX_EIGENVALUES, "header and library agree");
+static_assert(eeid::NLIST_MAX == EEID_NOALLOC_MAX_MATRICES, "header and library agree");
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
 }  // namespace
 
 struct eeid_handle_s {
@@ -53,6 +66,7 @@ struct eeid_handle_s {
     std::string err;
     Buf work, items, desc, desc_sub, dpair, dpair_sub, lam_ready;
     int *counter = nullptr;
+    char *scratch_ptr = nullptr;   // this device's copy of `scratch` (hipGetSymbolAddress at create)
     std::vector<int64_t> items_key, desc_key, desc_sub_key;
     int64_t n_items = 0;
     int variant = -1;           // >= 0: real-kernel configuration when the tune table has no entry
@@ -461,6 +475,13 @@ eeid_status_t eeid_create(eeid_handle_t *out, int hip_device) {
         delete h;
         return EEID_ERR_HIP;
     }
+    // with this device current: the address of its copy of the scratch array
+    if (hipGetSymbolAddress((void **)&h->scratch_ptr, HIP_SYMBOL(scratch)) != hipSuccess || !h->scratch_ptr) {
+        (void)hipGetLastError();
+        (void)hipFree(h->counter);
+        delete h;
+        return EEID_ERR_HIP;
+    }
     *out = h;
     return EEID_OK;
 }
@@ -565,6 +586,49 @@ eeid_status_t eeid_components(eeid_handle_t h, int64_t count, const int64_t *n, 
     Enqueue e;
     eeid_status_t s = prepare_components(h, count, n, lambda, mu, V2, flags, &e);
     return s != EEID_OK ? s : run_now(h, e);
+}
+
+eeid_status_t eeid_components_noalloc(eeid_handle_t h, int64_t count, const int64_t *n, const double *lambda,
+                                      const double *mu, double *V2, int32_t *flags) {
+    if (!h) return EEID_ERR_INVALID_ARG;
+    if (count < 1) return fail(h, EEID_ERR_INVALID_ARG, "count must be >= 1");
+    if (!n || !lambda || !V2 || !flags) return fail(h, EEID_ERR_INVALID_ARG, "null pointer argument");
+    if (count > eeid::NLIST_MAX)
+        return fail(h, EEID_ERR_UNSUPPORTED, "eeid_components_noalloc: count " + std::to_string(count) +
+                                                 " exceeds EEID_NOALLOC_MAX_MATRICES (" +
+                                                 std::to_string(eeid::NLIST_MAX) + ")");
+    eeid::NList nl;
+    nl.count = (int32_t)count;
+    int64_t nmax = 0, ntot = 0;
+    bool need_mu = false;
+    for (int64_t b = 0; b < count; ++b) {
+        if (n[b] < 1) return fail(h, EEID_ERR_INVALID_ARG, "n[" + std::to_string(b) + "] must be >= 1");
+        if (n[b] > EEID_MAX_N_R64) return fail(h, EEID_ERR_UNSUPPORTED, "n exceeds the supported maximum");
+        nl.n[b] = (int32_t)n[b];
+        nmax = std::max(nmax, n[b]);
+        ntot += n[b];
+        need_mu = need_mu || n[b] >= 2;
+    }
+    if (ntot > NOALLOC_MAX_EIGENVALUES)
+        return fail(h, EEID_ERR_UNSUPPORTED, "eeid_components_noalloc: sum of n is " + std::to_string(ntot) +
+                                                 ", above EEID_NOALLOC_MAX_EIGENVALUES (" +
+                                                 std::to_string(NOALLOC_MAX_EIGENVALUES) + ")");
+    if (need_mu && !mu) return fail(h, EEID_ERR_INVALID_ARG, "mu is null");
+    HIP_TRY(h, hipSetDevice(h->device));
+    eeid::BatchDesc *desc = reinterpret_cast<eeid::BatchDesc *>(h->scratch_ptr);
+    double *dpair = reinterpret_cast<double *>(h->scratch_ptr + NOALLOC_DESC_BYTES);
+    const unsigned ib = (unsigned)((nmax + 255) / 256);
+    const unsigned jb = (unsigned)((nmax + eeid::ID_JT - 1) / eeid::ID_JT);
+    hipStream_t st = h->stream;
+    // every scratch byte the later kernels read is written first (descriptors,
+    // then every denominator pair), so nothing needs clearing
+    hipLaunchKernelGGL(eeid::write_desc_kernel, dim3(1), dim3(64), 0, st, nl, desc);
+    hipLaunchKernelGGL(eeid::denominators_kernel, dim3(ib, (unsigned)count), dim3(256), 0, st, desc, lambda, dpair,
+                       flags);
+    hipLaunchKernelGGL(eeid::identity_kernel, dim3(ib, jb, (unsigned)count), dim3(256), 0, st, desc, lambda, mu,
+                       dpair, V2);
+    HIP_TRY(h, hipGetLastError());
+    return EEID_OK;
 }
 
 eeid_status_t eeid_components_subset(eeid_handle_t h, int64_t n, const double *lambda, int64_t nsel,

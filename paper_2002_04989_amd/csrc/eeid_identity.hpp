@@ -131,6 +131,30 @@ __global__ __launch_bounds__(256) void denominators_kernel(const BatchDesc *desc
     }
 }
 
+// Descriptors of up to NLIST_MAX matrices written on the device from their
+// orders (passed by value), for callers that cannot upload a table.
+constexpr int NLIST_MAX = 64;
+struct NList {
+    int32_t count;
+    int32_t n[NLIST_MAX];
+};
+__global__ __launch_bounds__(64) void write_desc_kernel(NList nl, BatchDesc *desc) {
+    if (threadIdx.x != 0) return;
+    int64_t lam = 0, mu = 0, v2 = 0;
+    for (int b = 0; b < nl.count; ++b) {
+        const int64_t n = nl.n[b];
+        desc[b].a_off = 0;
+        desc[b].lam_off = lam;
+        desc[b].mu_off = mu;
+        desc[b].v2_off = v2;
+        desc[b].n = (int32_t)n;
+        desc[b].ncol = (int32_t)n;
+        lam += n;
+        mu += n * (n - 1);
+        v2 += n * n;
+    }
+}
+
 constexpr int ID_JT = 8;    // minors (columns j) per thread
 constexpr int ID_KC = 256;  // minor eigenvalues staged per LDS chunk
 

@@ -25,7 +25,8 @@ STATUS = {0: "EEID_OK", 1: "EEID_ERR_INVALID_ARG", 2: "EEID_ERR_NO_DEVICE", 3: "
 EXPORTS = (
     "eeid_create", "eeid_destroy", "eeid_set_stream", "eeid_status_string", "eeid_last_error",
     "eeid_eigvalsh_batched", "eeid_minor_eigvals", "eeid_minor_eigvals_subset",
-    "eeid_components", "eeid_components_subset", "eeid_all_components", "eeid_set_graph_mode",
+    "eeid_components", "eeid_components_noalloc", "eeid_components_subset", "eeid_all_components",
+    "eeid_set_graph_mode",
     "eeid_variant_count", "eeid_set_variant",
     "eeid_autotune",
 )
@@ -66,6 +67,7 @@ def load_library(path: str = LIB_PATH):
     lib.eeid_minor_eigvals_subset.argtypes = [_vp, c, c, ctypes.c_int64, _vp, ctypes.c_int64, _i64p,
                                               _vp, _vp, _vp]
     lib.eeid_components.argtypes = [_vp, ctypes.c_int64, _i64p, _vp, _vp, _vp, _vp]
+    lib.eeid_components_noalloc.argtypes = [_vp, ctypes.c_int64, _i64p, _vp, _vp, _vp, _vp]
     lib.eeid_all_components.argtypes = [_vp, c, c, ctypes.c_int64, _i64p, _i64p, _vp, _vp, _vp, _vp, _vp]
     lib.eeid_components_subset.argtypes = [_vp, ctypes.c_int64, _vp, ctypes.c_int64, _vp, _vp, _vp]
     lib.eeid_set_graph_mode.argtypes = [_vp, c]
@@ -197,6 +199,16 @@ def components(lam, mu, n: Sequence[int], flags):
     _check(load_library().eeid_components(h, len(n), _i64(n), lam.data_ptr(),
                                            mu.data_ptr() if mu.numel() else None, V2.data_ptr(),
                                            flags.data_ptr()), h)
+    return V2
+
+
+def components_noalloc(lam, mu, n: Sequence[int], flags, V2):
+    """eeid_components into a caller-provided V2, with the library allocating nothing."""
+    n = [int(k) for k in n]
+    h = handle(lam.device.index)
+    _check(load_library().eeid_components_noalloc(h, len(n), _i64(n), lam.data_ptr(),
+                                                   mu.data_ptr() if mu.numel() else None, V2.data_ptr(),
+                                                   flags.data_ptr()), h)
     return V2
 
 
