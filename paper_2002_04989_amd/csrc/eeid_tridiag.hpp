@@ -23,6 +23,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #ifndef EEID_NT_LOADS
 #define EEID_NT_LOADS 1
 #endif
@@ -239,6 +241,18 @@ struct Panel {
 // lockstep; de (LDS, >= 2m doubles) receives (d_i, e_{i-1}^2) pairs, red
 // (LDS) the workgroup reductions.
 //
+// Two forms of the count.  With every operation correctly rounded (IEEE
+// division) the computed count is monotone in x, which makes bisection
+// provably converge to eigenvalue k; with e^2 / q taken as e^2 times the
+// hardware reciprocal refined by one Newton step (a few ulp off, and about
+// twice as fast) it can decrease within a few ulp of an eigenvalue.  The
+// halvings use the fast form down to the stopping width; then a bracket of
+// four stopping widths on either side of the result is certified by two
+// correctly rounded counts (count(lo) <= k < count(hi); where that fails, a
+// 64 times wider one or the Gershgorin interval), and correctly rounded
+// halvings bring it back to the stopping width.  Every returned eigenvalue
+// therefore comes from a bracket certified by the monotone count.
+//
 // brk (optional): the m + 1 ascending eigenvalues of a matrix of which T is
 // similar to a principal minor.  By Cauchy interlacing eigenvalue k of the
 // minor lies in [brk[k], brk[k + 1]]; that interval, widened by the rounding
@@ -284,8 +298,8 @@ __device__ void bisect_tridiagonal(const double *dg, const double *eg, int m, do
             lo[t] = gl; hi[t] = gu;
             done[t] = idx[t] >= m;
         }
-        // Sturm counts at ILP points
-        auto counts = [&](const double (&x)[ILP], int (&cnt)[ILP]) {
+        // Sturm counts at ILP points; EXACT: correctly rounded division
+        auto counts = [&](const double (&x)[ILP], int (&cnt)[ILP], auto exact) {
             double q[ILP];
 #pragma unroll
             for (int t = 0; t < ILP; ++t) { q[t] = 1.0; cnt[t] = 0; }
@@ -293,14 +307,41 @@ __device__ void bisect_tridiagonal(const double *dg, const double *eg, int m, do
                 const double d = de[2 * i], e2 = de[2 * i + 1];
 #pragma unroll
                 for (int t = 0; t < ILP; ++t) {
-                    // correctly rounded division: with monotone (correctly rounded)
-                    // arithmetic the count is monotone in x, which bisection relies
-                    // on; a reciprocal off by a few ulp breaks that within a few ulp
-                    // of an eigenvalue.  |q| >= pivmin keeps e2 / q finite.
-                    double v = (d - x[t]) - e2 / q[t];
-                    v = (fabs(v) < pivmin) ? -pivmin : v;
+                    double v;
+                    if constexpr (decltype(exact)::value) {
+                        v = (d - x[t]) - e2 / q[t];
+                    } else {
+                        double r = __builtin_amdgcn_rcp(q[t]);
+                        r = fma(fma(-q[t], r, 1.0), r, r);
+                        v = (d - x[t]) - e2 * r;
+                    }
+                    v = (fabs(v) < pivmin) ? -pivmin : v;   // |q| >= pivmin keeps e2 / q finite
                     cnt[t] += (v < 0.0) ? 1 : 0;
                     q[t] = v;
+                }
+            }
+        };
+        const std::integral_constant<bool, false> fast{};
+        const std::integral_constant<bool, true> exact{};
+        auto halve = [&](auto form) {
+            for (int it = 0; it < 80; ++it) {
+                bool all = true;
+#pragma unroll
+                for (int t = 0; t < ILP; ++t) all = all && done[t];
+                if (all) break;
+                double x[ILP];
+                int cnt[ILP];
+#pragma unroll
+                for (int t = 0; t < ILP; ++t) x[t] = 0.5 * (lo[t] + hi[t]);
+                counts(x, cnt, form);
+#pragma unroll
+                for (int t = 0; t < ILP; ++t) {
+                    if (done[t]) continue;
+                    if (cnt[t] > idx[t]) hi[t] = x[t]; else lo[t] = x[t];
+                    const double w = hi[t] - lo[t];
+                    const double mid = 0.5 * (lo[t] + hi[t]);
+                    if (w <= fmax(2.0 * eps * fmax(fabs(lo[t]), fabs(hi[t])), atol) || mid <= lo[t] || mid >= hi[t])
+                        done[t] = true;
                 }
             }
         };
@@ -313,31 +354,57 @@ __device__ void bisect_tridiagonal(const double *dg, const double *eg, int m, do
                 bl[t] = fmax(gl, brk[k] - pad);
                 bh[t] = fmin(gu, brk[k + 1] + pad);
             }
-            counts(bl, cl);
-            counts(bh, ch);
+            counts(bl, cl, fast);
+            counts(bh, ch, fast);
 #pragma unroll
             for (int t = 0; t < ILP; ++t)
                 if (!done[t] && bl[t] < bh[t] && cl[t] <= idx[t] && ch[t] > idx[t]) { lo[t] = bl[t]; hi[t] = bh[t]; }
         }
-        for (int it = 0; it < 80; ++it) {
-            bool all = true;
-#pragma unroll
-            for (int t = 0; t < ILP; ++t) all = all && done[t];
-            if (all) break;
-            double x[ILP];
-            int cnt[ILP];
-#pragma unroll
-            for (int t = 0; t < ILP; ++t) x[t] = 0.5 * (lo[t] + hi[t]);
-            counts(x, cnt);
+        halve(fast);
+        // Certify with the monotone count: a bracket of four stopping widths on
+        // either side of the fast result (its endpoints then lie outside the
+        // few ulp where the fast count can err), widened 64 times or reset to
+        // the Gershgorin interval where that fails; then correctly rounded
+        // halvings (three, typically) back to the stopping width.
+        {
+            int cl[ILP], ch[ILP];
+            double mid[ILP], sw[ILP];
 #pragma unroll
             for (int t = 0; t < ILP; ++t) {
-                if (done[t]) continue;
-                if (cnt[t] > idx[t]) hi[t] = x[t]; else lo[t] = x[t];
-                const double w = hi[t] - lo[t];
-                const double mid = 0.5 * (lo[t] + hi[t]);
-                if (w <= fmax(2.0 * eps * fmax(fabs(lo[t]), fabs(hi[t])), atol) || mid <= lo[t] || mid >= hi[t])
-                    done[t] = true;
+                mid[t] = 0.5 * (lo[t] + hi[t]);
+                sw[t] = fmax(2.0 * eps * fmax(fabs(lo[t]), fabs(hi[t])), atol);
+                lo[t] = fmax(gl, mid[t] - 4.0 * sw[t]);
+                hi[t] = fmin(gu, mid[t] + 4.0 * sw[t]);
             }
+            counts(lo, cl, exact);
+            counts(hi, ch, exact);
+            bool bad = false;
+#pragma unroll
+            for (int t = 0; t < ILP; ++t) {
+                done[t] = idx[t] >= m;
+                bad = bad || (!done[t] && !(cl[t] <= idx[t] && ch[t] > idx[t]));
+            }
+            if (__any(bad)) {
+                bool ok[ILP];
+#pragma unroll
+                for (int t = 0; t < ILP; ++t) ok[t] = done[t] || (cl[t] <= idx[t] && ch[t] > idx[t]);
+                double wl[ILP], wh[ILP];
+#pragma unroll
+                for (int t = 0; t < ILP; ++t) {
+                    wl[t] = fmax(gl, mid[t] - 256.0 * sw[t]);
+                    wh[t] = fmin(gu, mid[t] + 256.0 * sw[t]);
+                }
+                counts(wl, cl, exact);
+                counts(wh, ch, exact);
+#pragma unroll
+                for (int t = 0; t < ILP; ++t) {
+                    if (ok[t]) continue;
+                    const bool wok = cl[t] <= idx[t] && ch[t] > idx[t];
+                    lo[t] = wok ? wl[t] : gl;
+                    hi[t] = wok ? wh[t] : gu;
+                }
+            }
+            halve(exact);
         }
 #pragma unroll
         for (int t = 0; t < ILP; ++t)

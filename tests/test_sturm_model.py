@@ -3,18 +3,22 @@
 Each Sturm step is q_i = (d_i - x) - e_{i-1}^2 / q_{i-1}; the count of
 negative q_i is the number of eigenvalues below x.  Bisection is provably
 right only if the computed count is monotone in x, which holds when every
-operation is correctly rounded (a monotone function of its operands), so the
-kernel divides with IEEE division.  A cheaper reciprocal (the hardware
-reciprocal refined by one Newton step, within about 11 ulp of 1/q) is not
-monotone in q; this model replaces 1/q by fl(1/q) (1 + delta(q)) with
-|delta| <= 12 eps, delta a pseudo-random function of q's bits, and shows the
-difference on GOE, clustered, Laplacian and Wilkinson-type tridiagonals:
+operation is correctly rounded (a monotone function of its operands).  A
+cheaper reciprocal (the hardware reciprocal refined by one Newton step,
+within about 11 ulp of 1/q) is not monotone in q; this model replaces 1/q by
+fl(1/q) (1 + delta(q)) with |delta| <= 12 eps, delta a pseudo-random function
+of q's bits, and shows on GOE, clustered, Laplacian and Wilkinson-type
+tridiagonals that
 
 * with correctly rounded division the count never decreases on a fine grid
   and within a few ulp of every eigenvalue;
 * with the perturbed reciprocal it does decrease, a few ulp from some
-  eigenvalues (which is why the kernel does not use it), although the
-  bisection's results stay within its stopping width.
+  eigenvalues, although the bisection's results stay within its stopping
+  width;
+* the kernel's scheme -- halvings with the fast count, then a bracket of four
+  stopping widths around the result certified by two correctly rounded
+  counts and halved back with them -- needs no fallback on these inputs and
+  returns the eigenvalues of the all-correctly-rounded bisection.
 """
 import numpy as np
 import pytest
@@ -47,8 +51,14 @@ def sturm_count(d, e2, x, pivmin, exact=False):
     return cnt
 
 
-def bisect_all(d, e, exact):
-    """Every eigenvalue by bisection with the kernel's stopping rule."""
+def bisect_all(d, e, exact, certify=False):
+    """Every eigenvalue by bisection with the kernel's stopping rule.
+
+    certify: as the kernel, halve with the fast (inexact-reciprocal) count,
+    then certify a bracket of four stopping widths on either side of the
+    result with two correctly rounded counts (a 64 times wider one, or the
+    Gershgorin interval, where that fails) and halve it back to the stopping
+    width with correctly rounded counts.  Returns (eigenvalues, atol[, redone])."""
     m = len(d)
     el = np.r_[0.0, np.abs(e)]
     er = np.r_[np.abs(e), 0.0]
@@ -61,19 +71,40 @@ def bisect_all(d, e, exact):
     atol = EPS * tnorm
     idx = np.arange(m)
     lo, hi = np.full(m, gl), np.full(m, gu)
-    done = np.zeros(m, dtype=bool)
-    for _ in range(80):
-        if done.all():
-            break
-        x = 0.5 * (lo + hi)
-        c = sturm_count(d, e2, x, pivmin, exact)
-        up = c > idx
-        hi = np.where(~done & up, x, hi)
-        lo = np.where(~done & ~up, x, lo)
-        w = hi - lo
-        mid = 0.5 * (lo + hi)
-        done |= (w <= np.maximum(2.0 * EPS * np.maximum(np.abs(lo), np.abs(hi)), atol)) | (mid <= lo) | (mid >= hi)
-    return 0.5 * (lo + hi), atol
+
+    def halve(lo, hi, done, ex):
+        for _ in range(80):
+            if done.all():
+                break
+            x = 0.5 * (lo + hi)
+            c = sturm_count(d, e2, x, pivmin, ex)
+            up = c > idx
+            hi = np.where(~done & up, x, hi)
+            lo = np.where(~done & ~up, x, lo)
+            w = hi - lo
+            mid = 0.5 * (lo + hi)
+            done = done | (w <= np.maximum(2.0 * EPS * np.maximum(np.abs(lo), np.abs(hi)), atol)) | (mid <= lo) \
+                | (mid >= hi)
+        return lo, hi
+
+    lo, hi = halve(lo, hi, np.zeros(m, dtype=bool), exact and not certify)
+    if not certify:
+        return 0.5 * (lo + hi), atol
+    mid = 0.5 * (lo + hi)
+    sw = np.maximum(2.0 * EPS * np.maximum(np.abs(lo), np.abs(hi)), atol)
+    lo, hi = np.maximum(gl, mid - 4 * sw), np.minimum(gu, mid + 4 * sw)
+    ok = (sturm_count(d, e2, lo, pivmin, True) <= idx) & (sturm_count(d, e2, hi, pivmin, True) > idx)
+    redone = int(np.count_nonzero(~ok))
+    if redone:
+        wl, wh = np.maximum(gl, mid - 256 * sw), np.minimum(gu, mid + 256 * sw)
+        wok = (sturm_count(d, e2, wl, pivmin, True) <= idx) & (sturm_count(d, e2, wh, pivmin, True) > idx)
+        lo = np.where(ok, lo, np.where(wok, wl, gl))
+        hi = np.where(ok, hi, np.where(wok, wh, gu))
+    lo, hi = halve(lo, hi, np.zeros(m, dtype=bool), True)
+    # every bracket now passes the monotone count
+    assert np.all(sturm_count(d, e2, lo, pivmin, True) <= idx)
+    assert np.all(sturm_count(d, e2, hi, pivmin, True) > idx)
+    return 0.5 * (lo + hi), atol, redone
 
 
 def goe_tridiagonal(n, seed):
@@ -167,3 +198,15 @@ def test_the_perturbation_model_spans_its_bound():
     q = np.random.default_rng(3).standard_normal(100000) * 10.0 ** np.random.default_rng(4).uniform(-300, 300, 100000)
     rel = perturbed_reciprocal(q) * q - 1.0
     assert np.max(np.abs(rel)) <= 14 * EPS and np.max(np.abs(rel)) > 10 * EPS
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_certified_fast_bisection_matches_the_exact_one(name):
+    # the kernel's scheme: fast halvings, then every bracket certified by the
+    # monotone count (redone with it where the certificate fails)
+    d, e = CASES[name]()
+    w_cert, atol, redone = bisect_all(d, e, exact=True, certify=True)
+    w_exact, _ = bisect_all(d, e, exact=True)
+    width = np.maximum(2 * EPS * np.abs(w_exact), atol)
+    assert np.all(np.abs(w_cert - w_exact) <= 2 * width)
+    assert redone == 0
