@@ -76,10 +76,12 @@ typedef enum { EEID_PREC_FP64 = 0, EEID_PREC_FP32_TRAILING = 1 } eeid_prec_t;
 enum {
     EEID_FLAG_NONFINITE_INPUT = 1, /* a NaN/Inf in the lower triangle: all outputs of b are NaN */
     EEID_FLAG_DEGENERATE = 2,      /* lambda_i(A) repeated exactly: row i of V2 is NaN (Eq. (2) is 0/0) */
-    EEID_FLAG_WAIT_TIMEOUT = 4     /* a bounded wait between the waves of a workgroup gave up (a library
+    EEID_FLAG_WAIT_TIMEOUT = 4,    /* a bounded wait between the waves of a workgroup gave up (a library
                                       fault, never expected): the outputs of b are invalid.  The polls
                                       allowed (default 2^26) can be set by the environment variable
                                       EEID_SPIN_LIMIT, read by eeid_create */
+    EEID_FLAG_NO_REFERENCE = 8     /* eeid_signed_eigenvectors: some eigenvector has a zero component at
+                                      the reference index; its row of V is NaN */
 };
 
 /* Largest matrix order the library accepts (LDS holds two FP64/complex
@@ -182,6 +184,37 @@ eeid_status_t eeid_components_noalloc(eeid_handle_t h, int64_t count, const int6
 eeid_status_t eeid_components_subset(eeid_handle_t h, int64_t n, const double *lambda, int64_t nsel,
                                      const double *mu_sel, double *V2_sel, int32_t *flag);
 
+/* Signs of the eigenvector components (Section 2: the identity applied in
+ * other bases gives the directions).  For a reference index r and every
+ * partner k != r, B_k = R^T A R with R the rotation by pi/4 in the (r, k)
+ * plane (new basis e'_r = (e_r + e_k)/sqrt2, e'_k = (e_k - e_r)/sqrt2) has A's
+ * eigenvalues, and component r of its eigenvector i is (v_ir + v_ik)/sqrt2, so
+ * Eq. (2) on the minor of B_k at r gives (v_ir + v_ik)^2 / 2.
+ *
+ * eeid_rotated_minor_eigvals: the ascending spectra of those n - 1 minors
+ * (order n - 1 each) in one persistent launch, real symmetric A (EEID_R64)
+ * only (EEID_C128: EEID_ERR_UNSUPPORTED).
+ *   r       0 <= r < n
+ *   mu_rot  device [(n - 1) * (n - 1)] output, row q = spectrum for the q-th
+ *           partner k != r in ascending order
+ *   flag    device [1] output */
+eeid_status_t eeid_rotated_minor_eigvals(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64_t n,
+                                         const void *A, int64_t r, double *mu_rot, int32_t *flag);
+
+/* eeid_signed_eigenvectors: the unit eigenvectors with their signs, from
+ * lambda(A) and W (as eeid_all_components writes them for this matrix) and
+ * mu_rot: with S_ik the identity at r of B_k, v_ir v_ik = S_ik - (W_ir + W_ik)/2,
+ * and with the sign convention v_ir >= 0,
+ *   V[i * n + r] = sqrt(W_ir),  V[i * n + k] = (S_ik - (W_ir + W_ik)/2) / sqrt(W_ir).
+ * Row i is the eigenvector of the i-th smallest eigenvalue.  Its absolute
+ * error is about the error of W divided by sqrt(W_ir), so choose r where the
+ * eigenvectors of interest are not small.  A row with W_ir = 0 has no
+ * reference: it is NaN and bit 8 is OR-ed into *flag.
+ *   lambda device [n], W device [n * n], mu_rot device [(n - 1)^2]
+ *   V      device [n * n] output;  flag device [1] (bits OR-ed in) */
+eeid_status_t eeid_signed_eigenvectors(eeid_handle_t h, int64_t n, int64_t r, const double *lambda,
+                                       const double *W, const double *mu_rot, double *V, int32_t *flag);
+
 /* eeid_minor_eigvals followed by eeid_components: every |v_ij|^2 of every
  * matrix of the batch from device-resident A to device-resident V2.  In graph
  * mode (eeid_set_graph_mode) the launches are recorded once per argument set
@@ -191,6 +224,22 @@ eeid_status_t eeid_all_components(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p
                                   int64_t count, const int64_t *n, const int64_t *a_offset,
                                   const void *A, double *lambda, double *mu, double *V2,
                                   int32_t *flags);
+
+/* How the identity entry points (eeid_components, _noalloc, _subset and
+ * eeid_all_components) evaluate the ratio of Eq. (2); a property of the handle.
+ *  EEID_IDENTITY_PRODUCTS (default): numerator and denominator as two
+ *      products, each a mantissa with a separate integer exponent.
+ *  EEID_IDENTITY_PAIRED: Algorithm 2's pairing (Section 3): lambda_i taken
+ *      out, the other eigenvalues lambda'_k are paired in ascending order with
+ *      the minor's mu_k and W = prod_k |lambda_i - mu_k| / |lambda_i - lambda'_k|;
+ *      by Cauchy interlacing every factor is in [0, 1], so the running product
+ *      needs no exponent (it cannot underflow unless W does).  One correctly
+ *      rounded division per factor.
+ * Both give W within a few n eps (relative) of the exact ratio of the given
+ * spectra; flags and NaN/zero conventions are the same.  Returns
+ * EEID_ERR_INVALID_ARG for any other value. */
+typedef enum { EEID_IDENTITY_PRODUCTS = 0, EEID_IDENTITY_PAIRED = 1 } eeid_identity_form_t;
+eeid_status_t eeid_set_identity_form(eeid_handle_t h, int form);
 
 /* Enable (1) or disable (0) graph mode for eeid_all_components. */
 eeid_status_t eeid_set_graph_mode(eeid_handle_t h, int enable);

@@ -64,7 +64,7 @@ struct eeid_handle_s {
     hipStream_t stream = nullptr;
     int cu_count = 0;
     std::string err;
-    Buf work, items, desc, desc_sub, dpair, dpair_sub, lam_ready;
+    Buf work, items, desc, desc_sub, dpair, dpair_sub, lam_ready, sbuf;
     int *counter = nullptr;
     char *scratch_ptr = nullptr;   // this device's copy of `scratch` (hipGetSymbolAddress at create)
     std::vector<int64_t> items_key, desc_key, desc_sub_key;
@@ -73,6 +73,7 @@ struct eeid_handle_s {
     int forced_variant = -1;    // >= 0: use this configuration (autotuning, EEID_VARIANT)
     int64_t max_slots = 0;      // > 0: cap on resident problems (EEID_MAX_SLOTS)
     unsigned spin_limit = 1u << 26;   // polls before a bounded inter-wave wait gives up (EEID_SPIN_LIMIT)
+    int identity_form = EEID_IDENTITY_PRODUCTS;
     uint64_t generation = 0;    // bumped whenever a buffer the kernels read is reallocated or rewritten
     // graph mode
     bool graph_mode = false;
@@ -234,7 +235,8 @@ int pick_variant(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64_t nmax, i
 }
 
 // kind 0: eigenvalues of the matrices only; kind 1: matrices and all minors;
-// kind 2: one matrix and a subset of minors.
+// kind 2: one matrix and a subset of minors; kind 3: one matrix, the minors
+// at js[0] of its n - 1 rotated forms (partners k != js[0] ascending).
 eeid_status_t prepare_eigs(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64_t count, const int64_t *n,
                            const int64_t *a_offset, const void *A, double *lambda, double *mu, int32_t *flags,
                            int kind, int64_t nsel, const int64_t *js, Enqueue *out, int *variant_used = nullptr) {
@@ -251,26 +253,32 @@ eeid_status_t prepare_eigs(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64
         const int nb = (int)n[b];
         const double *src = Ad + esz * a_offset[b];
         nmax = std::max<int64_t>(nmax, nb);
-        if (lambda) items.push_back(Item{src, lambda + lam, nb, -1, nb, (int32_t)b});
+        if (lambda) items.push_back(Item{src, lambda + lam, nb, -1, nb, (int32_t)b, -1, 0});
         if (kind == 1 && nb >= 2)
             for (int j = 0; j < nb; ++j)
-                items.push_back(Item{src, mu + muo + (int64_t)j * (nb - 1), nb, j, nb - 1, (int32_t)b});
+                items.push_back(Item{src, mu + muo + (int64_t)j * (nb - 1), nb, j, nb - 1, (int32_t)b, -1, 0});
         if (kind == 2 && nb >= 2)
             for (int64_t q = 0; q < nsel; ++q)
-                items.push_back(Item{src, mu + q * (nb - 1), nb, (int)js[q], nb - 1, (int32_t)b});
+                items.push_back(Item{src, mu + q * (nb - 1), nb, (int)js[q], nb - 1, (int32_t)b, -1, 0});
+        // kind 3: minors at js[0] of the rotated matrices R^T A R, one per partner k != js[0]
+        if (kind == 3 && nb >= 2)
+            for (int k = 0, q = 0; k < nb; ++k)
+                if (k != (int)js[0])
+                    items.push_back(Item{src, mu + (int64_t)(q++) * (nb - 1), nb, (int)js[0], nb - 1, (int32_t)b, k, 0});
         lam += nb;
         muo += (int64_t)nb * (nb - 1);
     }
     // largest problems first so that the tail of the queue is short
     std::stable_sort(items.begin(), items.end(), [](const Item &x, const Item &y) { return x.m > y.m; });
     std::vector<int64_t> ikey;
-    ikey.reserve(4 * items.size() + 1);
+    ikey.reserve(5 * items.size() + 1);
     ikey.push_back((int64_t)items.size());
     for (const Item &it : items) {
         ikey.push_back((int64_t)(intptr_t)it.src);
         ikey.push_back((int64_t)(intptr_t)it.out);
         ikey.push_back(((int64_t)it.n << 32) | (uint32_t)it.j);
         ikey.push_back(((int64_t)it.m << 32) | (uint32_t)it.b);
+        ikey.push_back(it.k);
     }
     s = upload_table(h, h->items, h->items_key, ikey, items);
     if (s != EEID_OK) return s;
@@ -340,11 +348,17 @@ eeid_status_t prepare_identity(eeid_handle_t h, Buf &desc_buf, Buf &dpair_buf, i
     double *dpair = reinterpret_cast<double *>(dpair_buf.p);
     const unsigned ib = (unsigned)((nmax + 255) / 256);
     const unsigned jb = (unsigned)((ncol_max + eeid::ID_JT - 1) / eeid::ID_JT);
+    const bool paired = (h->identity_form == EEID_IDENTITY_PAIRED);
     *out = [=](hipStream_t st) -> hipError_t {
-        hipLaunchKernelGGL(eeid::denominators_kernel, dim3(ib, (unsigned)count), dim3(256), 0, st, desc, lambda,
-                           dpair, flags);
-        hipLaunchKernelGGL(eeid::identity_kernel, dim3(ib, jb, (unsigned)count), dim3(256), 0, st, desc, lambda, mu,
-                           dpair, V2);
+        if (paired) {
+            hipLaunchKernelGGL(eeid::identity_paired_kernel, dim3(ib, jb, (unsigned)count), dim3(256), 0, st, desc,
+                               lambda, mu, V2, flags);
+        } else {
+            hipLaunchKernelGGL(eeid::denominators_kernel, dim3(ib, (unsigned)count), dim3(256), 0, st, desc, lambda,
+                               dpair, flags);
+            hipLaunchKernelGGL(eeid::identity_kernel, dim3(ib, jb, (unsigned)count), dim3(256), 0, st, desc, lambda,
+                               mu, dpair, V2);
+        }
         return hipGetLastError();
     };
     return EEID_OK;
@@ -495,7 +509,7 @@ eeid_status_t eeid_destroy(eeid_handle_t h) {
     if (h->ev_in) (void)hipEventDestroy(h->ev_in);
     if (h->ev_out) (void)hipEventDestroy(h->ev_out);
     if (h->gstream) (void)hipStreamDestroy(h->gstream);
-    Buf *bufs[] = {&h->work, &h->items, &h->desc, &h->desc_sub, &h->dpair, &h->dpair_sub, &h->lam_ready};
+    Buf *bufs[] = {&h->work, &h->items, &h->desc, &h->desc_sub, &h->dpair, &h->dpair_sub, &h->lam_ready, &h->sbuf};
     for (Buf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (h->counter) (void)hipFree(h->counter);
@@ -512,6 +526,14 @@ eeid_status_t eeid_set_stream(eeid_handle_t h, void *stream) {
 eeid_status_t eeid_set_graph_mode(eeid_handle_t h, int enable) {
     if (!h) return EEID_ERR_INVALID_ARG;
     h->graph_mode = (enable != 0);
+    return EEID_OK;
+}
+
+eeid_status_t eeid_set_identity_form(eeid_handle_t h, int form) {
+    if (!h) return EEID_ERR_INVALID_ARG;
+    if (form != EEID_IDENTITY_PRODUCTS && form != EEID_IDENTITY_PAIRED)
+        return fail(h, EEID_ERR_INVALID_ARG, "unknown identity form");
+    h->identity_form = form;
     return EEID_OK;
 }
 
@@ -623,10 +645,15 @@ eeid_status_t eeid_components_noalloc(eeid_handle_t h, int64_t count, const int6
     // every scratch byte the later kernels read is written first (descriptors,
     // then every denominator pair), so nothing needs clearing
     hipLaunchKernelGGL(eeid::write_desc_kernel, dim3(1), dim3(64), 0, st, nl, desc);
-    hipLaunchKernelGGL(eeid::denominators_kernel, dim3(ib, (unsigned)count), dim3(256), 0, st, desc, lambda, dpair,
-                       flags);
-    hipLaunchKernelGGL(eeid::identity_kernel, dim3(ib, jb, (unsigned)count), dim3(256), 0, st, desc, lambda, mu,
-                       dpair, V2);
+    if (h->identity_form == EEID_IDENTITY_PAIRED) {
+        hipLaunchKernelGGL(eeid::identity_paired_kernel, dim3(ib, jb, (unsigned)count), dim3(256), 0, st, desc,
+                           lambda, mu, V2, flags);
+    } else {
+        hipLaunchKernelGGL(eeid::denominators_kernel, dim3(ib, (unsigned)count), dim3(256), 0, st, desc, lambda,
+                           dpair, flags);
+        hipLaunchKernelGGL(eeid::identity_kernel, dim3(ib, jb, (unsigned)count), dim3(256), 0, st, desc, lambda, mu,
+                           dpair, V2);
+    }
     HIP_TRY(h, hipGetLastError());
     return EEID_OK;
 }
@@ -645,6 +672,48 @@ eeid_status_t eeid_components_subset(eeid_handle_t h, int64_t n, const double *l
     Enqueue e;
     s = prepare_identity(h, h->desc_sub, h->dpair_sub, 1, n, nsel, n, lambda, mu_sel, V2_sel, flag, &e);
     return s != EEID_OK ? s : run_now(h, e);
+}
+
+eeid_status_t eeid_rotated_minor_eigvals(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64_t n,
+                                         const void *A, int64_t r, double *mu_rot, int32_t *flag) {
+    const int64_t zero = 0;
+    eeid_status_t s = check_batch(h, t, p, 1, &n, &zero, A);
+    if (s != EEID_OK) return s;
+    if (t != EEID_R64) return fail(h, EEID_ERR_UNSUPPORTED, "rotated minors: real symmetric input only");
+    if (r < 0 || r >= n) return fail(h, EEID_ERR_INVALID_ARG, "reference index r out of range");
+    if (!flag) return fail(h, EEID_ERR_INVALID_ARG, "null flag pointer");
+    if (n >= 2 && !mu_rot) return fail(h, EEID_ERR_INVALID_ARG, "mu_rot is null");
+    Enqueue e;
+    s = prepare_eigs(h, t, p, 1, &n, &zero, A, nullptr, mu_rot, flag, 3, 1, &r, &e);
+    return s != EEID_OK ? s : run_now(h, e);
+}
+
+eeid_status_t eeid_signed_eigenvectors(eeid_handle_t h, int64_t n, int64_t r, const double *lambda, const double *W,
+                                       const double *mu_rot, double *V, int32_t *flag) {
+    if (!h) return EEID_ERR_INVALID_ARG;
+    if (n < 1 || n > EEID_MAX_N_R64) return fail(h, EEID_ERR_INVALID_ARG, "n out of range");
+    if (r < 0 || r >= n) return fail(h, EEID_ERR_INVALID_ARG, "reference index r out of range");
+    if (!lambda || !W || !V || !flag || (n >= 2 && !mu_rot))
+        return fail(h, EEID_ERR_INVALID_ARG, "null pointer argument");
+    HIP_TRY(h, hipSetDevice(h->device));
+    double *S = nullptr;
+    Enqueue e;
+    if (n >= 2) {
+        const int64_t zero = 0;
+        eeid_status_t s = upload_desc(h, h->desc_sub, h->desc_sub_key, 1, &n, &zero, n - 1);
+        if (s != EEID_OK) return s;
+        s = ensure(h, h->sbuf, sizeof(double) * (size_t)(n * (n - 1)));
+        if (s != EEID_OK) return s;
+        S = reinterpret_cast<double *>(h->sbuf.p);
+        s = prepare_identity(h, h->desc_sub, h->dpair_sub, 1, n, n - 1, n, lambda, mu_rot, S, flag, &e);
+        if (s != EEID_OK) return s;
+        s = run_now(h, e);
+        if (s != EEID_OK) return s;
+    }
+    hipLaunchKernelGGL(eeid::signed_vectors_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)n), dim3(256), 0,
+                       h->stream, (int)n, (int)r, W, S, V, flag);
+    HIP_TRY(h, hipGetLastError());
+    return EEID_OK;
 }
 
 eeid_status_t eeid_all_components(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64_t count,
@@ -668,7 +737,7 @@ eeid_status_t eeid_all_components(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p
     }
     std::vector<int64_t> key = {(int64_t)t, (int64_t)p, count, (int64_t)(intptr_t)A, (int64_t)(intptr_t)lambda,
                                 (int64_t)(intptr_t)mu, (int64_t)(intptr_t)V2, (int64_t)(intptr_t)flags,
-                                (int64_t)h->generation, (int64_t)variant};
+                                (int64_t)h->generation, (int64_t)variant, (int64_t)h->identity_form};
     for (int64_t b = 0; b < count; ++b) { key.push_back(n[b]); key.push_back(a_offset[b]); }
     return run_graph(h, key, {e1, e2});
 }

@@ -80,7 +80,7 @@ struct Band {
                     if (row < m && col < m) {
                         const int rs = row + ((j >= 0 && row >= j) ? 1 : 0);
                         const int cs = col + ((j >= 0 && col >= j) ? 1 : 0);
-                        v = (rs >= cs) ? A[(int64_t)rs * n + cs] : A[(int64_t)cs * n + rs];
+                        v = (it.k >= 0) ? rotated_at(A, n, j, it.k, rs, cs) : lower_at(A, n, rs, cs);
                     }
                     __builtin_nontemporal_store((S)v, tp + q);
                 }

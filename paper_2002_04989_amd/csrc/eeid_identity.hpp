@@ -219,4 +219,94 @@ __global__ __launch_bounds__(256) void identity_kernel(const BatchDesc *desc, co
     }
 }
 
+// Signed eigenvectors from Eq. (2) in the original basis and in the n - 1
+// rotated bases of the (r, k) planes (Section 2: the identity applied in other
+// bases gives the directions).  W_ik = |v_ik|^2 (row-major, n x n); S holds,
+// for the q-th partner k != r (ascending), S[i (n-1) + q] = (v_ir + v_ik)^2 / 2,
+// the identity at r of the rotated matrix.  Then v_ir v_ik =
+// S_ik - (W_ir + W_ik) / 2 and, with the sign convention v_ir >= 0,
+// V[i n + k] = (S_ik - (W_ir + W_ik) / 2) / sqrt(W_ir), V[i n + r] = sqrt(W_ir).
+// A row with W_ir = 0 has no sign reference: it is NaN and flag bit 8 is set.
+__global__ __launch_bounds__(256) void signed_vectors_kernel(int n, int r, const double *W, const double *S,
+                                                              double *V, int32_t *flag) {
+    const int i = blockIdx.y;
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= n) return;
+    const double wr = W[(int64_t)i * n + r];
+    const double sr = sqrt(wr);
+    double v;
+    if (!(wr > 0.0)) {
+        v = __builtin_nan("");
+        if (k == 0) atomicOr(flag, 8);
+    } else if (k == r) {
+        v = sr;
+    } else {
+        const int q = k - (k > r ? 1 : 0);
+        v = (S[(int64_t)i * (n - 1) + q] - 0.5 * (wr + W[(int64_t)i * n + k])) / sr;
+    }
+    V[(int64_t)i * n + k] = v;
+}
+
+// Eq. (2) in the paired form of Algorithm 2 (Section 3): with lambda_i taken
+// out, the remaining eigenvalues lambda'_k (k = 1..n-1, ascending) are paired
+// with the ascending minor eigenvalues mu_jk, and
+//
+//   |v_ij|^2 = prod_k |lambda_i - mu_jk| / |lambda_i - lambda'_k|.
+//
+// By Cauchy interlacing (lambda_k <= mu_jk <= lambda_{k+1}) every paired
+// factor lies in [0, 1], so the running product only decreases: it needs no
+// exponent of its own and cannot underflow unless the result itself does.
+// Each factor is one correctly rounded division; the product runs over k in
+// ascending order.  Same launch geometry and LDS staging as identity_kernel;
+// an exactly zero denominator factor (repeated lambda_i) makes row i NaN and
+// sets the degenerate flag, an exactly zero numerator factor gives 0.
+__global__ __launch_bounds__(256) void identity_paired_kernel(const BatchDesc *desc, const double *lambda,
+                                                               const double *mu, double *V2, int32_t *flags) {
+    __shared__ double sm[ID_JT][ID_KC];
+    __shared__ double sl[ID_KC + 1];
+    const int b = blockIdx.z;
+    const int n = desc[b].n;
+    const int ncol = desc[b].ncol;
+    const int j0 = blockIdx.y * ID_JT;
+    if (j0 >= ncol || (int)blockIdx.x * 256 >= n) return;
+    const int m = n - 1;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const bool live = i < n;
+    const double *lam = lambda + desc[b].lam_off;
+    const int E = spectrum_exponent(lam, n);
+    const double li = live ? ldexp(lam[i], -E) : 0.0;
+    const double *mub = mu + desc[b].mu_off;
+    double r[ID_JT];
+#pragma unroll
+    for (int t = 0; t < ID_JT; ++t) r[t] = 1.0;
+    bool zero_den = false;
+    for (int kc = 0; kc < m; kc += ID_KC) {
+        const int kn = min(ID_KC, m - kc);
+        __syncthreads();
+        for (int q = threadIdx.x; q < ID_JT * ID_KC; q += 256) {
+            const int jj = q / ID_KC, kk = q % ID_KC;
+            const int j = j0 + jj;
+            sm[jj][kk] = (j < ncol && kk < kn) ? ldexp(mub[(int64_t)j * m + kc + kk], -E) : 0.0;
+        }
+        // lambda_{kc} .. lambda_{kc + kn}: lambda'_k is lambda_k below i, lambda_{k+1} from i on
+        for (int q = threadIdx.x; q <= kn; q += 256) sl[q] = ldexp(lam[kc + q], -E);
+        __syncthreads();
+        for (int kk = 0; kk < kn; ++kk) {
+            const double den = fabs(li - sl[kk + ((kc + kk >= i) ? 1 : 0)]);
+            zero_den = zero_den || den == 0.0;
+#pragma unroll
+            for (int t = 0; t < ID_JT; ++t) r[t] *= fabs(li - sm[t][kk]) / den;
+        }
+    }
+    if (!live) return;
+    if (zero_den) atomicOr(&flags[b], 2);
+    double *out = V2 + desc[b].v2_off + (int64_t)i * ncol;
+#pragma unroll
+    for (int t = 0; t < ID_JT; ++t) {
+        const int j = j0 + t;
+        if (j >= ncol) break;
+        out[j] = zero_den ? __builtin_nan("") : r[t];
+    }
+}
+
 }  // namespace eeid

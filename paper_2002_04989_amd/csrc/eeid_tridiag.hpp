@@ -42,7 +42,28 @@ struct Item {
     int32_t j;          // deleted row/column, -1 for the matrix itself
     int32_t m;          // order of the problem (n or n - 1)
     int32_t b;          // batch index (flags)
+    int32_t k;          // >= 0: the minor is taken of R^T A R, R the pi/4 rotation in the (j, k) plane
+    int32_t pad;
 };
+
+// Element (p, q) of the symmetric matrix whose lower triangle is A (row-major, order n).
+__device__ __forceinline__ double lower_at(const double *A, int n, int p, int q) {
+    return (p >= q) ? A[(int64_t)p * n + q] : A[(int64_t)q * n + p];
+}
+
+// Element (p, q), p, q != r, of B = R^T A R with R the rotation by pi/4 in the
+// (r, k) plane: new basis vectors e'_r = (e_r + e_k)/sqrt2, e'_k = (e_k - e_r)/sqrt2,
+// the others unchanged.  B has A's eigenvalues, and component r of its
+// eigenvector i is (v_ir + v_ik)/sqrt2, so Eq. (2) applied to B at r gives
+// (v_ir + v_ik)^2 / 2 (the identity in another basis, Section 2).  Of the
+// minor without row and column r only row and column k differ from A's.
+__device__ __forceinline__ double rotated_at(const double *A, int n, int r, int k, int p, int q) {
+    constexpr double h = 0.70710678118654752440;   // 1/sqrt2
+    if (p == k && q == k) return 0.5 * (lower_at(A, n, k, k) - 2.0 * lower_at(A, n, r, k) + lower_at(A, n, r, r));
+    if (p == k) return h * (lower_at(A, n, k, q) - lower_at(A, n, r, q));
+    if (q == k) return h * (lower_at(A, n, p, k) - lower_at(A, n, p, r));
+    return lower_at(A, n, p, q);
+}
 
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 typedef float fvec4 __attribute__((ext_vector_type(4)));
@@ -453,7 +474,7 @@ struct Tri {
                     if (row < m && col < m) {
                         const int rs = row + ((j >= 0 && row >= j) ? 1 : 0);
                         const int cs = col + ((j >= 0 && col >= j) ? 1 : 0);
-                        v = (rs >= cs) ? A[(int64_t)rs * n + cs] : A[(int64_t)cs * n + rs];
+                        v = (it.k >= 0) ? rotated_at(A, n, j, it.k, rs, cs) : lower_at(A, n, rs, cs);
                     }
                     tp[q] = (S)v;
                 }

@@ -19,6 +19,7 @@ PREC = {"fp64": 0, "fp32": 1}
 FLAG_NONFINITE_INPUT = 1
 FLAG_DEGENERATE = 2
 FLAG_WAIT_TIMEOUT = 4
+FLAG_NO_REFERENCE = 8
 STATUS = {0: "EEID_OK", 1: "EEID_ERR_INVALID_ARG", 2: "EEID_ERR_NO_DEVICE", 3: "EEID_ERR_ALLOC",
           4: "EEID_ERR_HIP", 5: "EEID_ERR_UNSUPPORTED"}
 
@@ -27,7 +28,8 @@ EXPORTS = (
     "eeid_eigvalsh_batched", "eeid_minor_eigvals", "eeid_minor_eigvals_subset",
     "eeid_components", "eeid_components_noalloc", "eeid_components_subset", "eeid_all_components",
     "eeid_set_graph_mode",
-    "eeid_variant_count", "eeid_set_variant",
+    "eeid_variant_count", "eeid_set_variant", "eeid_set_identity_form",
+    "eeid_rotated_minor_eigvals", "eeid_signed_eigenvectors",
     "eeid_autotune",
 )
 VARIANTS = ("nb32_nt512", "nb32_nt256x2", "nb16_nt512", "band32_nt512", "band32_nt256x2")
@@ -71,6 +73,9 @@ def load_library(path: str = LIB_PATH):
     lib.eeid_all_components.argtypes = [_vp, c, c, ctypes.c_int64, _i64p, _i64p, _vp, _vp, _vp, _vp, _vp]
     lib.eeid_components_subset.argtypes = [_vp, ctypes.c_int64, _vp, ctypes.c_int64, _vp, _vp, _vp]
     lib.eeid_set_graph_mode.argtypes = [_vp, c]
+    lib.eeid_set_identity_form.argtypes = [_vp, c]
+    lib.eeid_rotated_minor_eigvals.argtypes = [_vp, c, c, ctypes.c_int64, _vp, ctypes.c_int64, _vp, _vp]
+    lib.eeid_signed_eigenvectors.argtypes = [_vp, ctypes.c_int64, ctypes.c_int64, _vp, _vp, _vp, _vp, _vp]
     lib.eeid_variant_count.argtypes = []
     lib.eeid_variant_count.restype = c
     lib.eeid_set_variant.argtypes = [_vp, c]
@@ -232,6 +237,16 @@ def set_graph_mode(enable: bool, device: int | None = None):
     _check(load_library().eeid_set_graph_mode(h, 1 if enable else 0), h)
 
 
+IDENTITY_FORMS = ("products", "paired")
+
+
+def set_identity_form(form: str, device: int | None = None):
+    """Evaluate Eq. (2) as two products with exponents ("products", default) or
+    with Algorithm 2's paired factors in [0, 1] ("paired")."""
+    h = handle(device)
+    _check(load_library().eeid_set_identity_form(h, IDENTITY_FORMS.index(form)), h)
+
+
 def set_variant(variant, device: int | None = None):
     """Force a real-kernel configuration (name from VARIANTS or index), or None for automatic."""
     h = handle(device)
@@ -275,6 +290,36 @@ def all_components(mats, prec: str = "fp64"):
                                                flat.data_ptr(), lam.data_ptr(), mu.data_ptr(), V2.data_ptr(),
                                                flags.data_ptr()), h)
     return lam, mu[:nm], V2, flags
+
+
+def rotated_minor_eigvals(A, r: int, prec: str = "fp64"):
+    """Spectra of the minors at r of the n - 1 rotated matrices R^T A R: (mu_rot [n-1, n-1], flag)."""
+    import torch
+    if not A.is_cuda or A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("A must be a square GPU tensor")
+    A = A.contiguous()
+    n = int(A.shape[0])
+    mu_rot = torch.empty((max(n - 1, 1), max(n - 1, 1)), dtype=torch.float64, device=A.device)
+    flag = torch.empty(1, dtype=torch.int32, device=A.device)
+    h = handle(A.device.index)
+    _check(load_library().eeid_rotated_minor_eigvals(h, _dtype_code(A), PREC[prec], n, A.data_ptr(), int(r),
+                                                      mu_rot.data_ptr(), flag.data_ptr()), h)
+    return mu_rot[:n - 1, :n - 1], flag
+
+
+def signed_eigenvectors(A, r: int = 0, prec: str = "fp64"):
+    """Unit eigenvectors with signs (v_ir >= 0) from Eq. (2) in the original and
+    the rotated bases: (lambda, V [n, n] with row i the i-th eigenvector, flags)."""
+    import torch
+    n = int(A.shape[0])
+    lam, mu, V2, flags = all_components(A, prec)
+    mu_rot, flag_rot = rotated_minor_eigvals(A, r, prec)
+    V = torch.empty((n, n), dtype=torch.float64, device=A.device)
+    h = handle(A.device.index)
+    _check(load_library().eeid_signed_eigenvectors(h, n, int(r), lam.data_ptr(), V2.data_ptr(),
+                                                    mu_rot.data_ptr() if n > 1 else None, V.data_ptr(),
+                                                    flags.data_ptr()), h)
+    return lam, V, flags | flag_rot
 
 
 def split(vec, n: Sequence[int], kind: str):

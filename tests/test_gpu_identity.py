@@ -4,6 +4,8 @@
   in tests/test_identity_model.py (same IEEE operations in the same order),
   on GOE spectra that span several LDS chunks of minor eigenvalues and a
   ragged tail.
+* The paired form (Algorithm 2's factors in [0, 1]) is bit for bit its own
+  CPU model and agrees with the products form.
 * Graded spectra: diag(g, 2g, 3g, 1) gives W = I exactly for g down to the
   subnormal range, and blockdiag(2^-k B, C) reproduces the components of B
   and C computed at unit scale, although single factors are of order 2^-k.
@@ -23,21 +25,58 @@ import pytest
 import oracle
 from paper_2002_04989_amd import inputs
 from tests.gpu_util import announce
-from tests.test_identity_model import graded_block_spectra, identity_model
+from tests.test_identity_model import graded_block_spectra, identity_model, paired_model
 
 pytestmark = pytest.mark.gpu
 
 
-def gpu_components(lam, mu_rows):
+def gpu_components(lam, mu_rows, form="products"):
     import torch
     from paper_2002_04989_amd import eeid
     n = len(lam)
     dl = torch.from_numpy(np.ascontiguousarray(lam, dtype=np.float64)).to("cuda:0")
     dm = torch.from_numpy(np.ascontiguousarray(np.asarray(mu_rows, dtype=np.float64).reshape(-1))).to("cuda:0")
     flags = torch.zeros(1, dtype=torch.int32, device="cuda:0")
-    V2 = eeid.components(dl, dm, [n], flags)
-    torch.cuda.synchronize()
+    eeid.set_identity_form(form)
+    try:
+        V2 = eeid.components(dl, dm, [n], flags)
+        torch.cuda.synchronize()
+    finally:
+        eeid.set_identity_form("products")
     return V2.cpu().numpy().reshape(n, n), int(flags.cpu()[0])
+
+
+@pytest.mark.parametrize("n", [2, 9, 300, 517])
+def test_paired_kernel_is_the_model_bit_for_bit(n):
+    announce(f"paired identity kernel vs model, GOE spectra n={n}")
+    A = inputs.goe(n, 300 + n)
+    lam = oracle.eigvalsh(A, "lapack")
+    mu = oracle.minor_spectra(A, range(n), "lapack")
+    W, flag = gpu_components(lam, mu, "paired")
+    assert flag == 0
+    js = sorted(set([0, n // 2, n - 1]))
+    np.testing.assert_array_equal(W[:, js], paired_model(lam, mu[js]))
+    W_prod, _ = gpu_components(lam, mu)
+    assert np.max(np.abs(W - W_prod)) < 1e-13 * max(1, n / 16)
+
+
+@pytest.mark.parametrize("k", [332, 1020])
+def test_paired_graded_block_spectra(k):
+    announce(f"paired identity kernel, graded blocks 2^-{k}")
+    lam, mu, W_exp = graded_block_spectra(k)
+    W, flag = gpu_components(lam, mu, "paired")
+    assert flag == 0
+    np.testing.assert_array_equal(W, paired_model(lam, mu))
+    assert np.max(np.abs(W - W_exp)) < 1e-13
+
+
+def test_paired_conventions():
+    announce("paired identity kernel: zero factor, degenerate row")
+    W, flag = gpu_components(np.array([-1.0, 0.0, 2.0]), np.array([[0.0, 2.0], [-1.0, 2.0], [-1.0, 0.0]]), "paired")
+    assert flag == 0 and np.all(np.isfinite(W))
+    np.testing.assert_array_equal(W, np.eye(3))
+    W, flag = gpu_components(np.array([1.0, 1.0, 3.0]), np.array([[1.0, 3.0], [1.0, 3.0], [1.0, 1.0]]), "paired")
+    assert flag & 2 and np.all(np.isnan(W[:2])) and np.all(np.isfinite(W[2]))
 
 
 @pytest.mark.parametrize("n", [2, 9, 300, 517])

@@ -89,6 +89,65 @@ def identity_model(lam, mu_rows):
     return W
 
 
+def paired_factors(lam, mu, i):
+    """Algorithm 2's paired factors |lambda_i - mu_k| / |lambda_i - lambda'_k|,
+    lambda' = lambda without lambda_i, both ascending (scaled as the kernel)."""
+    lam = np.asarray(lam, dtype=np.float64)
+    E = spectrum_exponent(lam)
+    ls = [math.ldexp(float(x), -E) for x in lam]
+    ms = [math.ldexp(float(x), -E) for x in mu]
+    m = len(ls) - 1
+    return [abs(ls[i] - ms[k]) / abs(ls[i] - ls[k + (1 if k >= i else 0)]) for k in range(m)]
+
+
+def paired_model(lam, mu_rows):
+    """The paired kernel's W[i, t]: the factors multiplied in ascending k."""
+    n = len(lam)
+    W = np.empty((n, len(mu_rows)))
+    for i in range(n):
+        lam_ = np.asarray(lam, dtype=np.float64)
+        lam_other = np.delete(lam_, i)
+        if np.any(lam_other == lam_[i]):
+            W[i, :] = math.nan
+            continue
+        for t, mu in enumerate(mu_rows):
+            r = 1.0
+            for f in paired_factors(lam, mu, i):
+                r *= f
+            W[i, t] = r
+    return W
+
+
+@pytest.mark.parametrize("n, seed", [(2, 1), (17, 2), (64, 3), (150, 4), (300, 6)])
+def test_paired_factors_lie_in_the_unit_interval_and_multiply_to_w(n, seed):
+    # Cauchy interlacing puts every paired factor in [0, 1] (to rounding), so
+    # the running product never grows; it reproduces the oracle's log sums
+    a = np.random.default_rng(seed).standard_normal((n, n))
+    a = (a + a.T) / np.sqrt(2)
+    lam = oracle.eigvalsh(a, "lapack")
+    js = list(range(0, n, max(1, n // 6)))
+    mu = oracle.minor_spectra(a, js, "lapack")
+    fmax = max(max(paired_factors(lam, mu[t], i)) for i in range(n) for t in range(len(js))) if n > 1 else 0.0
+    assert fmax <= 1.0 + 1e-9
+    W_log, _ = oracle.identity_from_spectra(lam, mu)
+    W = paired_model(lam, mu)
+    assert np.max(np.abs(W - W_log)) < 1e-13 * max(1, n / 16)
+
+
+@pytest.mark.parametrize("k", [332, 1020])
+def test_paired_form_on_graded_blocks(k):
+    lam, mu, W_exp = graded_block_spectra(k)
+    W = paired_model(lam, mu)
+    assert np.max(np.abs(W - W_exp)) < 1e-13
+
+
+def test_paired_form_zero_factor_and_degenerate_row():
+    W = paired_model(np.array([-1.0, 0.0, 2.0]), np.array([[0.0, 1.0]]))
+    assert W[1, 0] == 0.0 and np.all(np.isfinite(W))
+    W = paired_model(np.array([1.0, 1.0, 3.0]), np.array([[1.0, 2.0]]))
+    assert np.all(np.isnan(W[0])) and np.all(np.isnan(W[1])) and np.isfinite(W[2, 0])
+
+
 @pytest.mark.parametrize("n, seed", [(2, 1), (17, 2), (64, 3), (150, 4), (300, 6)])
 def test_model_matches_the_oracles_log_sums(n, seed):
     a = np.random.default_rng(seed).standard_normal((n, n))

@@ -283,3 +283,69 @@ def test_planted_mistakes_are_caught():
     }
     for name, fn in planted.items():
         assert not _pins_pass(fn), f"pins did not catch: {name}"
+
+
+# ------------------------------------------------------ signs from rotated bases
+def laplacian_vectors(n):
+    """Rows: unit eigenvectors of tridiag(-1, 2, -1), ascending eigenvalues (sine closed form)."""
+    k = np.arange(1, n + 1)
+    return np.sqrt(2.0 / (n + 1)) * np.sin(np.outer(k, k) * np.pi / (n + 1))
+
+
+@pytest.mark.parametrize("n, r", [(1, 0), (2, 1), (9, 0), (9, 3), (40, 7)])
+def test_signed_eigenvectors_laplacian_closed_form(n, r):
+    L = 2 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)
+    Vx = laplacian_vectors(n)
+    Vx = Vx * np.where(Vx[:, r] < 0, -1.0, 1.0)[:, None]
+    zero_ref = np.abs(Vx[:, r]) < 1e-12            # sin(jk pi / (n + 1)) = 0
+    _, Vd = oracle.signed_eigenvectors_definition(L, r)
+    assert np.max(np.abs(Vd[~zero_ref] - Vx[~zero_ref])) < 1e-13
+    _, Vi = oracle.signed_eigenvectors_identity(L, r)
+    assert np.all(np.isnan(Vi[zero_ref])) and not np.any(np.isnan(Vi[~zero_ref]))
+    assert np.max(np.abs(Vi[~zero_ref] - Vx[~zero_ref])) < 1e-12
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_signed_eigenvectors_2x2_closed_form(seed):
+    r = np.random.default_rng(seed)
+    a, b, c = r.standard_normal(3)
+    A = np.array([[a, b], [b, c]])
+    lam, _ = closed_2x2(a, b, c)
+    for ref in (0, 1):
+        # eigenvector of lambda: (b, lambda - a) up to scale; sign so that component ref >= 0
+        Vx = np.array([[b, l - a] for l in lam])
+        Vx /= np.linalg.norm(Vx, axis=1)[:, None]
+        Vx *= np.where(Vx[:, ref] < 0, -1.0, 1.0)[:, None]
+        _, Vi = oracle.signed_eigenvectors_identity(A, ref)
+        assert np.max(np.abs(Vi - Vx)) < 1e-13
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_signed_eigenvectors_method_matches_definition_tiny(seed):
+    r = np.random.default_rng(1000 + seed)
+    n = int(r.integers(2, 9))
+    G = r.standard_normal((n, n))
+    A = (G + G.T) / 2
+    ref = int(r.integers(0, n))
+    _, Vd = oracle.signed_eigenvectors_definition(A, ref)
+    _, Vi = oracle.signed_eigenvectors_identity(A, ref)
+    # the method's error is the error of W over sqrt(W_ir): compare rows with a usable reference
+    ok = Vd[:, ref] ** 2 > 1e-6
+    assert np.max(np.abs(Vi[ok] - Vd[ok])) < 1e-10
+    # and it is an orthonormal basis of eigenvectors
+    np.testing.assert_allclose(Vi[ok] @ A.T, (np.linalg.eigvalsh(A)[ok, None]) * Vi[ok], atol=1e-9)
+
+
+def test_rotated_minor_is_the_minor_of_a_similar_matrix():
+    A = inputs.goe(10, 5)
+    lam = oracle.eigvalsh(A)
+    _, V = oracle.signed_eigenvectors_definition(A, 2)
+    for k in (0, 5, 9):
+        R = O.rotation(10, 2, k)
+        np.testing.assert_allclose(R.T @ R, np.eye(10), atol=1e-15)
+        np.testing.assert_allclose(oracle.eigvalsh(R.T @ A @ R), lam, atol=1e-13)
+        mu = oracle.eigvalsh(oracle.rotated_minor(A, 2, k))
+        assert np.all(lam[:-1] <= mu + 1e-13) and np.all(mu <= lam[1:] + 1e-13)
+        # Eq. (2) at r on the rotated matrix gives (v_ir + v_ik)^2 / 2
+        S, _ = oracle.identity_from_spectra(lam, mu[None, :])
+        np.testing.assert_allclose(S[:, 0], 0.5 * (V[:, 2] + V[:, k]) ** 2, atol=1e-12)

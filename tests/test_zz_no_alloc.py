@@ -64,6 +64,17 @@ def test_noalloc_batch_and_flags():
     assert f[2] & eeid.FLAG_DEGENERATE and not np.any(np.delete(f, 2))
 
 
+def test_noalloc_paired_form():
+    announce("components_noalloc, paired form")
+    eeid.set_identity_form("paired")
+    try:
+        V, V_ref, f, f_ref = run_both([spectra(300, 5), spectra(41, 6)])
+    finally:
+        eeid.set_identity_form("products")
+    np.testing.assert_array_equal(V, V_ref)
+    np.testing.assert_array_equal(f, f_ref)
+
+
 def test_noalloc_limits_are_refused():
     import torch
     announce("components_noalloc limits")
