@@ -184,6 +184,16 @@ eeid_status_t eeid_components_noalloc(eeid_handle_t h, int64_t count, const int6
 eeid_status_t eeid_components_subset(eeid_handle_t h, int64_t n, const double *lambda, int64_t nsel,
                                      const double *mu_sel, double *V2_sel, int32_t *flag);
 
+/* One eigenvector's squared components (the complete-eigenvector query of
+ * Section 4, Fig. 1(b)): row i of Eq. (2), row[j] = |v_ij|^2 for every j, from
+ * lambda(A) and the spectra of all n minors (as eeid_minor_eigvals writes
+ * them for this matrix), in the handle's identity form; bit for bit row i of
+ * eeid_components' V2.
+ *   lambda device [n];  mu device [n * (n - 1)];  0 <= i < n
+ *   row    device [n] output;  flag device [1], EEID_FLAG_DEGENERATE is OR-ed in */
+eeid_status_t eeid_eigenvector_sq(eeid_handle_t h, int64_t n, const double *lambda, const double *mu, int64_t i,
+                                  double *row, int32_t *flag);
+
 /* Signs of the eigenvector components (Section 2: the identity applied in
  * other bases gives the directions).  For a reference index r and every
  * partner k != r, B_k = R^T A R with R the rotation by pi/4 in the (r, k)

@@ -317,6 +317,7 @@ eeid_status_t prepare_eigs(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64
     a.slot_bytes = kc.slot;
     a.LDmax = LDmax;
     a.spin_limit = h->spin_limit;
+    a.wait_lambda = (lambda != nullptr) ? 1 : 0;
     const eeid::BatchDesc *desc = reinterpret_cast<const eeid::BatchDesc *>(h->desc.p);
     const unsigned nn_blocks = (unsigned)((nmax * nmax + 4095) / 4096);
     const int cplx = (t == EEID_C128) ? 1 : 0;
@@ -672,6 +673,24 @@ eeid_status_t eeid_components_subset(eeid_handle_t h, int64_t n, const double *l
     Enqueue e;
     s = prepare_identity(h, h->desc_sub, h->dpair_sub, 1, n, nsel, n, lambda, mu_sel, V2_sel, flag, &e);
     return s != EEID_OK ? s : run_now(h, e);
+}
+
+eeid_status_t eeid_eigenvector_sq(eeid_handle_t h, int64_t n, const double *lambda, const double *mu, int64_t i,
+                                  double *row, int32_t *flag) {
+    if (!h) return EEID_ERR_INVALID_ARG;
+    if (n < 1 || n > EEID_MAX_N_R64) return fail(h, EEID_ERR_INVALID_ARG, "n out of range");
+    if (i < 0 || i >= n) return fail(h, EEID_ERR_INVALID_ARG, "eigenvalue index i out of range");
+    if (!lambda || !row || !flag || (n >= 2 && !mu)) return fail(h, EEID_ERR_INVALID_ARG, "null pointer argument");
+    HIP_TRY(h, hipSetDevice(h->device));
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (h->identity_form == EEID_IDENTITY_PAIRED)
+        hipLaunchKernelGGL(eeid::eigenvector_row_kernel<true>, grid, dim3(256), 0, h->stream, (int)n, (int)i, lambda,
+                           mu, row, flag);
+    else
+        hipLaunchKernelGGL(eeid::eigenvector_row_kernel<false>, grid, dim3(256), 0, h->stream, (int)n, (int)i, lambda,
+                           mu, row, flag);
+    HIP_TRY(h, hipGetLastError());
+    return EEID_OK;
 }
 
 eeid_status_t eeid_rotated_minor_eigvals(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64_t n,

@@ -477,8 +477,9 @@ struct Band {
     }
 
     // ------------------------------------------------------------ W from Y
-    // X = Y T (rows >= r0), M = V^T X (matrix cores, LDS atomics), N = T^T M,
-    // W = X - 1/2 V N; rows [J1*64, r0) of W are zero.
+    // X = Y T (rows >= r0), M = V^T X (matrix cores), N = T^T M,
+    // W = X - 1/2 V N; rows [J1*64, r0) of W are zero.  M is summed over the
+// waves in a fixed order (no atomics), so a rerun gives the same bits.
     // Rows [r0, LD) of Z = X2 - s * Y2 Q (in place in Wm when X2 = Wm), in
     // 16-row blocks on matrix cores: Z^T = X2^T - s * Q^T Y2^T, with Q (BW x BW)
     // in LDS (Q(k, n) at q[k * BW + n]).  For a block of rows rb..rb+15,
@@ -520,8 +521,10 @@ struct Band {
         // X = Y T (T upper triangular, its lower part zero in LDS); each block's Y
         // is read before its X is written, by the same wave
         rows_times_small<false>(r0, Wm, Tm, 0.0);
-        for (int q = tid; q < BW * BW; q += NT) Mm[q] = 0.0;
         __syncthreads();
+        // per-wave partial sums of M, added in wave order afterwards (a fixed
+        // order: reruns give the same bits)
+        double *part = Nm + BW * BW;
         {
             // M(i, j) = sum_r V(r, i) X(r, j): rows in chunks of 4 per MFMA, chunks dealt to waves
             const int lr = lane & 15, lk = lane >> 4;
@@ -547,7 +550,13 @@ struct Band {
                 for (int jb = 0; jb < 2; ++jb)
 #pragma unroll
                     for (int g = 0; g < 4; ++g)
-                        atomicAdd(&Mm[(ib * 16 + lk + 4 * g) * BW + jb * 16 + lr], acc[ib][jb][g]);
+                        part[wave * BW * BW + (ib * 16 + lk + 4 * g) * BW + jb * 16 + lr] = acc[ib][jb][g];
+        }
+        __syncthreads();
+        for (int q = tid; q < BW * BW; q += NT) {
+            double sum = part[q];
+            for (int w = 1; w < NWAVE; ++w) sum += part[w * BW * BW + q];
+            Mm[q] = sum;
         }
         __syncthreads();
         for (int q = tid; q < BW * BW; q += NT) {
@@ -1152,7 +1161,8 @@ __host__ __device__ inline int64_t slot_bytes_band(int LDmax) {
 template <int NT>
 __host__ __device__ inline int64_t lds_big_band(int LDmax) {
     constexpr int64_t nw = NT / 64;
-    const int64_t stage1 = 4 * BW * TILE;   // T, M, N (3 BW^2), then the SYR2K staging of two tile columns
+    // T, M, N (3 BW^2) and the per-wave partial sums of M; then the SYR2K staging of two tile columns
+    const int64_t stage1 = (4 * BW * TILE > (3 + nw) * BW * BW) ? 4 * BW * TILE : (3 + nw) * BW * BW;
     const int64_t chase = nw * (6 * BW + 2 * 40 + 2 * 16 * 64) + (nw + 1) / 2;
     const int64_t bis = 2 * (int64_t)LDmax;
     return (stage1 > chase ? (stage1 > bis ? stage1 : bis) : (chase > bis ? chase : bis));

@@ -309,4 +309,61 @@ __global__ __launch_bounds__(256) void identity_paired_kernel(const BatchDesc *d
     }
 }
 
+// Row i of Eq. (2) only (one eigenvector's squared components, all j), from
+// lambda and the spectra of all n minors: one thread per column j, each
+// reading its minor's spectrum directly.  The arithmetic is that of
+// denominators_kernel + identity_kernel (PAIRED false: same factors, same
+// grouping into chunks of ID_KC with renormalisation every RENORM factors) or
+// of identity_paired_kernel (PAIRED true), so the row is bit for bit the
+// corresponding row of the full W.
+template <bool PAIRED>
+__global__ __launch_bounds__(256) void eigenvector_row_kernel(int n, int i, const double *lam, const double *mu,
+                                                               double *row, int32_t *flag) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    const int m = n - 1;
+    const int E = spectrum_exponent(lam, n);
+    const double li = ldexp(lam[i], -E);
+    const double *muj = mu + (int64_t)j * m;
+    double w;
+    if constexpr (PAIRED) {
+        double r = 1.0;
+        bool zero_den = false;
+        for (int k = 0; k < m; ++k) {
+            const double den = fabs(li - ldexp(lam[k + (k >= i ? 1 : 0)], -E));
+            zero_den = zero_den || den == 0.0;
+            r *= fabs(li - ldexp(muj[k], -E)) / den;
+        }
+        w = zero_den ? __builtin_nan("") : r;
+        if (zero_den && j == 0) atomicOr(flag, 2);
+    } else {
+        double q = 1.0;
+        int qe = 0, cnt = 0;
+        bool zero = false;
+        for (int k = 0; k < n; ++k) {
+            if (k == i) continue;
+            const double d = li - ldexp(lam[k], -E);
+            if (d == 0.0) zero = true;
+            mul_factor(q, qe, fabs(d));
+            if (++cnt == RENORM) { renormalise(q, qe); cnt = 0; }
+        }
+        renormalise(q, qe);
+        double pm = 1.0;
+        int pe = 0;
+        for (int kc = 0; kc < m; kc += ID_KC) {
+            const int kn = min(ID_KC, m - kc);
+            int kk = 0;
+            for (; kk + RENORM <= kn; kk += RENORM) {
+                for (int u = 0; u < RENORM; ++u) mul_factor(pm, pe, fabs(li - ldexp(muj[kc + kk + u], -E)));
+                renormalise(pm, pe);
+            }
+            for (; kk < kn; ++kk) mul_factor(pm, pe, fabs(li - ldexp(muj[kc + kk], -E)));
+            renormalise(pm, pe);
+        }
+        w = zero ? __builtin_nan("") : ldexp(pm / q, pe - qe);
+        if (zero && j == 0) atomicOr(flag, 2);
+    }
+    row[j] = w;
+}
+
 }  // namespace eeid

@@ -933,19 +933,41 @@ struct TriArgs {
     // polls after which a wave waiting for another wave of its workgroup gives
     // up (bounded waits: the problem is then flagged, and the kernel still ends)
     unsigned spin_limit;
+    // 1: every matrix's own problem is in this launch, so its minors wait for
+    // its eigenvalues (interlacing brackets independent of timing)
+    int wait_lambda;
 };
 
 // flags bit of a problem whose bounded inter-wave wait gave up (its outputs are invalid)
 constexpr int32_t FLAG_WAIT_TIMEOUT = 4;
 
 // Bracket source for the bisection of item `it`: the eigenvalues of its
-// matrix if it is a minor and they are already final (published by the
-// workgroup that computed them), else nullptr.  Uniform over the workgroup;
-// s_flag is LDS scratch.
+// matrix if it is a plain minor (published by the workgroup that computed
+// them), else nullptr.  When the launch holds every matrix's own problem
+// (a.wait_lambda), a minor waits for them -- bounded by a.spin_limit polls,
+// after which it flags FLAG_WAIT_TIMEOUT and bisects from the Gershgorin
+// interval -- so that the starting bracket, and with it every bit of the
+// result, does not depend on timing.  The wait always ends: the matrix's own
+// problem has the larger order, so the queue (largest first) hands it out
+// before any of its minors, and it waits for nothing.  Uniform over the
+// workgroup; s_flag is LDS scratch.
 __device__ inline const double *interlacing_bracket(const TriArgs &a, const Item &it, unsigned long long *s_flag) {
-    if (it.j < 0) return nullptr;
-    if (threadIdx.x == 0)
-        *s_flag = __hip_atomic_load(&a.lam_ready[it.b], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    if (it.j < 0 || it.k >= 0) return nullptr;
+    if (threadIdx.x == 0) {
+        unsigned long long p = __hip_atomic_load(&a.lam_ready[it.b], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        if (a.wait_lambda) {
+            unsigned polls = 0;
+            while (p == 0) {
+                if (++polls > a.spin_limit) {
+                    atomicOr(&a.flags[it.b], FLAG_WAIT_TIMEOUT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(8);
+                p = __hip_atomic_load(&a.lam_ready[it.b], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        *s_flag = p;
+    }
     __syncthreads();
     const unsigned long long p = *s_flag;
     __syncthreads();

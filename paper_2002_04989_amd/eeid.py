@@ -29,7 +29,7 @@ EXPORTS = (
     "eeid_components", "eeid_components_noalloc", "eeid_components_subset", "eeid_all_components",
     "eeid_set_graph_mode",
     "eeid_variant_count", "eeid_set_variant", "eeid_set_identity_form",
-    "eeid_rotated_minor_eigvals", "eeid_signed_eigenvectors",
+    "eeid_rotated_minor_eigvals", "eeid_signed_eigenvectors", "eeid_eigenvector_sq",
     "eeid_autotune",
 )
 VARIANTS = ("nb32_nt512", "nb32_nt256x2", "nb16_nt512", "band32_nt512", "band32_nt256x2")
@@ -74,6 +74,7 @@ def load_library(path: str = LIB_PATH):
     lib.eeid_components_subset.argtypes = [_vp, ctypes.c_int64, _vp, ctypes.c_int64, _vp, _vp, _vp]
     lib.eeid_set_graph_mode.argtypes = [_vp, c]
     lib.eeid_set_identity_form.argtypes = [_vp, c]
+    lib.eeid_eigenvector_sq.argtypes = [_vp, ctypes.c_int64, _vp, _vp, ctypes.c_int64, _vp, _vp]
     lib.eeid_rotated_minor_eigvals.argtypes = [_vp, c, c, ctypes.c_int64, _vp, ctypes.c_int64, _vp, _vp]
     lib.eeid_signed_eigenvectors.argtypes = [_vp, ctypes.c_int64, ctypes.c_int64, _vp, _vp, _vp, _vp, _vp]
     lib.eeid_variant_count.argtypes = []
@@ -290,6 +291,17 @@ def all_components(mats, prec: str = "fp64"):
                                                flat.data_ptr(), lam.data_ptr(), mu.data_ptr(), V2.data_ptr(),
                                                flags.data_ptr()), h)
     return lam, mu[:nm], V2, flags
+
+
+def eigenvector_sq(lam, mu, i: int, flag):
+    """Row i of Eq. (2): |v_ij|^2 for every j, from lambda and all minors' spectra of one matrix."""
+    import torch
+    n = int(lam.numel())
+    row = torch.empty(n, dtype=torch.float64, device=lam.device)
+    h = handle(lam.device.index)
+    _check(load_library().eeid_eigenvector_sq(h, n, lam.data_ptr(), mu.data_ptr() if mu.numel() else None, int(i),
+                                               row.data_ptr(), flag.data_ptr()), h)
+    return row
 
 
 def rotated_minor_eigvals(A, r: int, prec: str = "fp64"):

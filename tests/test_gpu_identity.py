@@ -172,3 +172,42 @@ def test_bounded_wait_gives_up_and_flags():
     from tests.gpu_util import run_all
     _, _, _, flag = run_all([inputs.goe(n, 9)])[0]
     assert flag == 0
+
+
+@pytest.mark.parametrize("form", ["products", "paired"])
+@pytest.mark.parametrize("n", [2, 300, 517])
+def test_eigenvector_sq_is_the_row_of_w(n, form):
+    import torch
+    from paper_2002_04989_amd import eeid
+    announce(f"eigenvector_sq n={n} {form}")
+    A = inputs.goe(n, 900 + n)
+    lam = oracle.eigvalsh(A, "lapack")
+    mu = oracle.minor_spectra(A, range(n), "lapack")
+    W, _ = gpu_components(lam, mu, form)
+    dl = torch.from_numpy(lam).to("cuda:0")
+    dm = torch.from_numpy(mu.reshape(-1)).to("cuda:0")
+    flag = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    eeid.set_identity_form(form)
+    try:
+        rows = {i: eeid.eigenvector_sq(dl, dm, i, flag) for i in sorted({0, n // 2, n - 1})}
+        torch.cuda.synchronize()
+    finally:
+        eeid.set_identity_form("products")
+    assert int(flag.cpu()[0]) == 0
+    for i, row in rows.items():
+        np.testing.assert_array_equal(row.cpu().numpy(), W[i])
+    W_log, _ = oracle.identity_from_spectra(lam, mu)
+    for i, row in rows.items():
+        assert np.max(np.abs(row.cpu().numpy() - W_log[i])) < 1e-13 * max(1, n / 16)
+
+
+def test_eigenvector_sq_degenerate_row():
+    import torch
+    from paper_2002_04989_amd import eeid
+    announce("eigenvector_sq degenerate")
+    lam = torch.tensor([1.0, 1.0, 3.0], dtype=torch.float64, device="cuda:0")
+    mu = torch.tensor([1.0, 3.0, 1.0, 3.0, 1.0, 1.0], dtype=torch.float64, device="cuda:0")
+    flag = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    r0 = eeid.eigenvector_sq(lam, mu, 0, flag).cpu().numpy()
+    r2 = eeid.eigenvector_sq(lam, mu, 2, flag).cpu().numpy()
+    assert np.all(np.isnan(r0)) and np.all(np.isfinite(r2)) and int(flag.cpu()[0]) & 2
