@@ -324,6 +324,71 @@ def host_library(mats, budget_s=8.0):
                       f"problems (EigenValues step only)"}
 
 
+# Table 1 of the paper (Section 4): one component of one eigenvector on a 4-core
+# Xeon E3-1270 v6 (NumPy eigh / Algorithm 2, seconds, mean of 10 runs).  Context only.
+PAPER_TABLE1 = {502: (0.170962, 0.119722), 1002: (1.100800, 0.595935), 2002: (9.522480, 3.212001),
+                3002: (30.342656, 9.522745), 4002: (69.955400, 16.775200), 5002: (134.324200, 30.547200),
+                6002: (229.338600, 50.682400)}
+
+
+def single_component_latency(sizes=(502, 1002, 2002, 3002, 4002, 5002, 6002), reps=3, oracle_n=502):
+    """The single-component query of Table 1 (lambda(A) + the spectrum of one minor
+    M_j + Eq. (2), here for every i of column j at once) on one GOE matrix per
+    size: the latency path (each problem over many workgroups) against the
+    batched path (one workgroup per problem), wall time from device-resident A
+    to device-resident column; and the oracle (extended-precision Jacobi, both
+    problems on two threads at once, plus the log-sum column) at oracle_n,
+    scaled by n^3 to the other sizes."""
+    import numpy as np
+    import torch
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_2002_04989_amd import eeid, inputs
+    rows = []
+    for n in sizes:
+        A = torch.from_numpy(inputs.goe(n, 11)).to("cuda:0")
+        j = n // 2
+        res = {}
+        for path in ("latency", "batched"):
+            ts = []
+            for _ in range(reps + 1):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if path == "latency":
+                    lam, mu, flag = eeid.minor_eigvals_latency(A, [j])
+                else:
+                    lam, mu, flag = eeid.minor_eigvals_subset(A, [j])
+                W = eeid.components_subset(lam, mu, flag)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            res[path] = (sorted(ts[1:])[len(ts[1:]) // 2] * 1e3, W.cpu().numpy()[:, 0], int(flag.cpu()[0]))
+        row = {"n": n, "latency_path_ms": round(res["latency"][0], 2), "batched_path_ms": round(res["batched"][0], 2),
+               "max_abs_dW_latency_vs_batched": float(np.max(np.abs(res["latency"][1] - res["batched"][1]))),
+               "flags": [res["latency"][2], res["batched"][2]]}
+        if n in PAPER_TABLE1:
+            row["paper_table1_s"] = {"numpy_eigh": PAPER_TABLE1[n][0], "algorithm2": PAPER_TABLE1[n][1]}
+        rows.append(row)
+        log(f"single component n={n}: latency path {row['latency_path_ms']} ms, batched {row['batched_path_ms']} ms")
+        del A
+    out = {"workload": "GOE (seed 11) of each order n, one minor j = n // 2; lambda(A) + mu(M_j) + column j of W",
+           "rows": rows, "paper_hardware": "Intel Xeon E3-1270 v6, 4 cores / 8 threads (context only)"}
+    if oracle_n is None:
+        return out
+    # the oracle at oracle_n: lambda(A) and M_j by Jacobi on two threads, then the column
+    A = inputs.goe(oracle_n, 11)
+    j = oracle_n // 2
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(2) as ex:
+        lam, mu = ex.map(lambda M: oracle.eigvalsh(M), [A, oracle.minor(A, j)])
+    oracle.identity_from_spectra(lam, mu[None, :])
+    t_or = time.perf_counter() - t0
+    for row in rows:
+        row["oracle_s"] = round(t_or * (row["n"] / oracle_n) ** 3, 2)
+        row["oracle_kind"] = "measured" if row["n"] == oracle_n else f"n^3-scaled from the measured n={oracle_n}"
+    out["oracle"] = f"extended-precision Jacobi, 2 threads ({cpu_model()}), {t_or:.1f} s at n={oracle_n}"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -333,6 +398,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 trailing-update form")
     ap.add_argument("--no-tune", action="store_true", help="skip the (untimed) autotuning of kernel configurations")
     ap.add_argument("--no-paired", action="store_true", help="skip timing the paired form of the identity")
+    ap.add_argument("--no-latency", action="store_true", help="skip the single-component latency table")
     ap.add_argument("--copy-ref", action="store_true",
                     help="run a 1 GiB device copy first (reference for HBM counter scaling)")
     args = ap.parse_args()
@@ -416,6 +482,10 @@ def main():
                 "errors_vs_oracle": errors(mats, truth, h32[0], h32[1], h32[2], n),
                 "flags": [int(x) for x in h32[3]]}
 
+    latency = None
+    if not args.no_latency:
+        log("single-component latency (Table 1 sizes)")
+        latency = single_component_latency(oracle_n=None if args.no_cpu else 502)
     cpu = hostlib = None
     if not args.no_cpu:
         log("cpu baseline (oracle) on a bounded sample")
@@ -437,6 +507,7 @@ def main():
         "errors_vs_oracle": err64, "flags": flags64,
         "fp32_form": fp32,
         "identity_paired_form": paired,
+        "single_component_latency": latency,
         "kernel_sources_hash": kernel_sources_hash(),
     }
     print(json.dumps(out), flush=True)

@@ -8,7 +8,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 SRC = os.path.join(PKG, "csrc", "eeid.hip")
-DEPS = [os.path.join(PKG, "csrc", f) for f in ("eeid.hip", "eeid_tridiag.hpp", "eeid_tridiag_c.hpp", "eeid_band.hpp", "eeid_identity.hpp")]
+DEPS = [os.path.join(PKG, "csrc", f) for f in ("eeid.hip", "eeid_tridiag.hpp", "eeid_tridiag_c.hpp", "eeid_band.hpp", "eeid_identity.hpp", "eeid_latency.hpp")]
 LIB = os.path.join(PKG, "libeeid.so")
 ARCH = "gfx950"
 

@@ -25,6 +25,7 @@
 #include "eeid.h"
 #include "eeid_band.hpp"
 #include "eeid_identity.hpp"
+#include "eeid_latency.hpp"
 #include "eeid_tridiag.hpp"
 #include "eeid_tridiag_c.hpp"
 
@@ -64,7 +65,7 @@ struct eeid_handle_s {
     hipStream_t stream = nullptr;
     int cu_count = 0;
     std::string err;
-    Buf work, items, desc, desc_sub, dpair, dpair_sub, lam_ready, sbuf;
+    Buf work, items, desc, desc_sub, dpair, dpair_sub, lam_ready, sbuf, lat_work, lat_items, lat_bar;
     int *counter = nullptr;
     char *scratch_ptr = nullptr;   // this device's copy of `scratch` (hipGetSymbolAddress at create)
     std::vector<int64_t> items_key, desc_key, desc_sub_key;
@@ -510,7 +511,8 @@ eeid_status_t eeid_destroy(eeid_handle_t h) {
     if (h->ev_in) (void)hipEventDestroy(h->ev_in);
     if (h->ev_out) (void)hipEventDestroy(h->ev_out);
     if (h->gstream) (void)hipStreamDestroy(h->gstream);
-    Buf *bufs[] = {&h->work, &h->items, &h->desc, &h->desc_sub, &h->dpair, &h->dpair_sub, &h->lam_ready, &h->sbuf};
+    Buf *bufs[] = {&h->work,     &h->items,     &h->desc,    &h->desc_sub, &h->dpair, &h->dpair_sub,
+                   &h->lam_ready, &h->sbuf, &h->lat_work, &h->lat_items, &h->lat_bar};
     for (Buf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (h->counter) (void)hipFree(h->counter);
@@ -601,6 +603,83 @@ eeid_status_t eeid_minor_eigvals_subset(eeid_handle_t h, eeid_dtype_t t, eeid_pr
     Enqueue e;
     s = prepare_eigs(h, t, p, 1, &n, &zero, A, lambda, mu_sel, flag, 2, nsel, js, &e);
     return s != EEID_OK ? s : run_now(h, e);
+}
+
+eeid_status_t eeid_minor_eigvals_latency(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64_t n,
+                                         const void *A, int64_t nsel, const int64_t *js, double *lambda,
+                                         double *mu_sel, int32_t *flag) {
+    const int64_t zero = 0;
+    eeid_status_t s = check_batch(h, t, p, 1, &n, &zero, A);
+    if (s != EEID_OK) return s;
+    if (t != EEID_R64 || p != EEID_PREC_FP64)
+        return fail(h, EEID_ERR_UNSUPPORTED, "latency path: real symmetric input in the FP64 form only");
+    if (nsel < 0 || (nsel > 0 && !js)) return fail(h, EEID_ERR_INVALID_ARG, "nsel must be >= 0 and js non-null");
+    if (!flag) return fail(h, EEID_ERR_INVALID_ARG, "null flag pointer");
+    if (nsel > 0 && n >= 2 && !mu_sel) return fail(h, EEID_ERR_INVALID_ARG, "mu_sel is null");
+    for (int64_t q = 0; q < nsel; ++q)
+        if (js[q] < 0 || js[q] >= n) return fail(h, EEID_ERR_INVALID_ARG, "js entry out of range");
+    std::vector<eeid::Item> items;
+    const double *src = reinterpret_cast<const double *>(A);
+    if (lambda) items.push_back(eeid::Item{src, lambda, (int32_t)n, -1, (int32_t)n, 0, -1, 0});
+    if (n >= 2)
+        for (int64_t q = 0; q < nsel; ++q)
+            items.push_back(eeid::Item{src, mu_sel + q * (n - 1), (int32_t)n, (int32_t)js[q], (int32_t)(n - 1), 0, -1, 0});
+    if ((int64_t)items.size() > eeid::LAT_MAX_PROBLEMS)
+        return fail(h, EEID_ERR_UNSUPPORTED, "latency path: at most " + std::to_string(eeid::LAT_MAX_PROBLEMS) +
+                                                 " problems per call");
+    HIP_TRY(h, hipSetDevice(h->device));
+    s = upload_desc(h, h->desc_sub, h->desc_sub_key, 1, &n, &zero, 1);
+    if (s != EEID_OK) return s;
+    const eeid::BatchDesc *desc = reinterpret_cast<const eeid::BatchDesc *>(h->desc_sub.p);
+    const int P = (int)items.size();
+    int coop = 0;
+    HIP_TRY(h, hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, h->device));
+    if (!coop) return fail(h, EEID_ERR_UNSUPPORTED, "device does not support cooperative launches");
+    const int LD = (int)((n + 7) / 8 * 8);
+    const size_t lds = (size_t)eeid::lat_lds_bytes(LD);
+    const void *kern = (const void *)eeid::latency_eig_kernel;
+    HIP_TRY(h, hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    int per_cu = 0;
+    HIP_TRY(h, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, eeid::LAT_NT, lds));
+    if (per_cu < 1) return fail(h, EEID_ERR_UNSUPPORTED, "latency kernel cannot be resident");
+    // one workgroup per CU, split evenly over the problems
+    const int G = std::max(1, h->cu_count / std::max(P, 1));
+    const int64_t pb = eeid::lat_prob_bytes(LD, G);
+    if (P > 0) {
+        s = ensure(h, h->lat_work, (size_t)(pb * P));
+        if (s != EEID_OK) return s;
+        s = ensure(h, h->lat_bar, sizeof(unsigned) * eeid::LAT_MAX_PROBLEMS);
+        if (s != EEID_OK) return s;
+        s = ensure(h, h->lat_items, sizeof(eeid::Item) * eeid::LAT_MAX_PROBLEMS);
+        if (s != EEID_OK) return s;
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        HIP_TRY(h, hipMemcpy(h->lat_items.p, items.data(), sizeof(eeid::Item) * P, hipMemcpyHostToDevice));
+    }
+    hipStream_t st = h->stream;
+    unsigned *bar = reinterpret_cast<unsigned *>(h->lat_bar.p);
+    hipLaunchKernelGGL(eeid::prep_kernel, dim3(1), dim3(256), 0, st, flag, (int64_t)1, (int *)nullptr,
+                       (unsigned long long *)nullptr);
+    hipLaunchKernelGGL(eeid::nonfinite_kernel, dim3((unsigned)((n * n + 4095) / 4096), 1u), dim3(256), 0, st, desc,
+                       src, 0, flag);
+    if (P == 0) {
+        HIP_TRY(h, hipGetLastError());
+        return EEID_OK;
+    }
+    hipLaunchKernelGGL(eeid::reset_barriers_kernel, dim3(1), dim3(64), 0, st, bar, P);
+    eeid::LatArgs a;
+    a.items = reinterpret_cast<const eeid::Item *>(h->lat_items.p);
+    a.P = P;
+    a.G = G;
+    a.work = reinterpret_cast<char *>(h->lat_work.p);
+    a.prob_bytes = pb;
+    a.LD = LD;
+    a.bar = bar;
+    a.flags = flag;
+    a.spin_limit = h->spin_limit >> 6;   // a grid barrier's poll is a device-scope load (~64 times an LDS poll)
+    void *argv[] = {&a};
+    HIP_TRY(h, hipLaunchCooperativeKernel(kern, dim3((unsigned)(P * G)), dim3(eeid::LAT_NT), argv, (unsigned)lds, st));
+    HIP_TRY(h, hipGetLastError());
+    return EEID_OK;
 }
 
 eeid_status_t eeid_components(eeid_handle_t h, int64_t count, const int64_t *n, const double *lambda,

@@ -281,7 +281,9 @@ struct Panel {
 // when the counts confirm it (else the Gershgorin interval is kept).
 template <int NT, int ILP>
 __device__ void bisect_tridiagonal(const double *dg, const double *eg, int m, double *out, double *de,
-                                   double *red, int tid, int lane, int wave, const double *brk = nullptr) {
+                                   double *red, int tid, int lane, int wave, const double *brk = nullptr,
+                                   int i_begin = 0, int i_end = -1) {
+    const int ie = (i_end < 0) ? m : i_end;   // eigenvalues i_begin .. ie - 1 (all by default)
     constexpr int NWAVE = NT / 64;
     double gl = 1e308, gu = -1e308, emax2 = 0.0;
     for (int i = tid; i < m; i += NT) {
@@ -309,7 +311,7 @@ __device__ void bisect_tridiagonal(const double *dg, const double *eg, int m, do
     const double pad = 2.0 * eps * tnorm * (double)m + 4.0 * pivmin;
     gl -= pad; gu += pad;
     const double atol = eps * tnorm;
-    for (int base = 0; base < m; base += NT * ILP) {
+    for (int base = i_begin; base < ie; base += NT * ILP) {
         double lo[ILP], hi[ILP];
         int idx[ILP];
         bool done[ILP];
@@ -317,7 +319,7 @@ __device__ void bisect_tridiagonal(const double *dg, const double *eg, int m, do
         for (int t = 0; t < ILP; ++t) {
             idx[t] = base + t * NT + tid;
             lo[t] = gl; hi[t] = gu;
-            done[t] = idx[t] >= m;
+            done[t] = idx[t] >= ie;
         }
         // Sturm counts at ILP points; EXACT: correctly rounded division
         auto counts = [&](const double (&x)[ILP], int (&cnt)[ILP], auto exact) {
@@ -402,7 +404,7 @@ __device__ void bisect_tridiagonal(const double *dg, const double *eg, int m, do
             bool bad = false;
 #pragma unroll
             for (int t = 0; t < ILP; ++t) {
-                done[t] = idx[t] >= m;
+                done[t] = idx[t] >= ie;
                 bad = bad || (!done[t] && !(cl[t] <= idx[t] && ch[t] > idx[t]));
             }
             if (__any(bad)) {
@@ -429,7 +431,7 @@ __device__ void bisect_tridiagonal(const double *dg, const double *eg, int m, do
         }
 #pragma unroll
         for (int t = 0; t < ILP; ++t)
-            if (idx[t] < m) out[idx[t]] = 0.5 * (lo[t] + hi[t]);
+            if (idx[t] < ie) out[idx[t]] = 0.5 * (lo[t] + hi[t]);
     }
 }
 

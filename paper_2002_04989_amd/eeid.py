@@ -30,6 +30,7 @@ EXPORTS = (
     "eeid_set_graph_mode",
     "eeid_variant_count", "eeid_set_variant", "eeid_set_identity_form",
     "eeid_rotated_minor_eigvals", "eeid_signed_eigenvectors", "eeid_eigenvector_sq",
+    "eeid_minor_eigvals_latency",
     "eeid_autotune",
 )
 VARIANTS = ("nb32_nt512", "nb32_nt256x2", "nb16_nt512", "band32_nt512", "band32_nt256x2")
@@ -74,6 +75,8 @@ def load_library(path: str = LIB_PATH):
     lib.eeid_components_subset.argtypes = [_vp, ctypes.c_int64, _vp, ctypes.c_int64, _vp, _vp, _vp]
     lib.eeid_set_graph_mode.argtypes = [_vp, c]
     lib.eeid_set_identity_form.argtypes = [_vp, c]
+    lib.eeid_minor_eigvals_latency.argtypes = [_vp, c, c, ctypes.c_int64, _vp, ctypes.c_int64, _i64p,
+                                               _vp, _vp, _vp]
     lib.eeid_eigenvector_sq.argtypes = [_vp, ctypes.c_int64, _vp, _vp, ctypes.c_int64, _vp, _vp]
     lib.eeid_rotated_minor_eigvals.argtypes = [_vp, c, c, ctypes.c_int64, _vp, ctypes.c_int64, _vp, _vp]
     lib.eeid_signed_eigenvectors.argtypes = [_vp, ctypes.c_int64, ctypes.c_int64, _vp, _vp, _vp, _vp, _vp]
@@ -194,6 +197,32 @@ def minor_eigvals_subset(A, js: Sequence[int], prec: str = "fp64", with_lambda: 
         h, _dtype_code(A), PREC[prec], n, A.data_ptr(), len(js), _i64(js),
         lam.data_ptr() if lam is not None else None, mu.data_ptr(), flag.data_ptr()), h)
     return lam, mu[:, :n - 1], flag
+
+
+def minor_eigvals_latency(A, js: Sequence[int], prec: str = "fp64", with_lambda: bool = True):
+    """As minor_eigvals_subset, each problem spread over many workgroups (few problems, low latency)."""
+    import torch
+    if not A.is_cuda or A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("A must be a square GPU tensor")
+    A = A.contiguous()
+    n = int(A.shape[0])
+    dev = A.device
+    lam = torch.empty(n, dtype=torch.float64, device=dev) if with_lambda else None
+    mu = torch.empty((max(len(js), 1), max(n - 1, 1)), dtype=torch.float64, device=dev)
+    flag = torch.empty(1, dtype=torch.int32, device=dev)
+    h = handle(dev.index)
+    _check(load_library().eeid_minor_eigvals_latency(
+        h, _dtype_code(A), PREC[prec], n, A.data_ptr(), len(js), _i64(js) if len(js) else None,
+        lam.data_ptr() if lam is not None else None, mu.data_ptr(), flag.data_ptr()), h)
+    return lam, mu[:len(js), :n - 1], flag
+
+
+def component_column(A, j: int):
+    """|v_ij|^2 for every i and one j (the single-component query of Algorithm 2 for
+    all i at once): lambda(A) and the spectrum of M_j on the latency path, then Eq. (2)."""
+    lam, mu, flag = minor_eigvals_latency(A, [int(j)])
+    W = components_subset(lam, mu, flag)
+    return W[:, 0], lam, mu[0], flag
 
 
 def components(lam, mu, n: Sequence[int], flags):
