@@ -16,8 +16,10 @@ at any size:
   (tests/golden/*.npz, written by tests/golden/make_golden.py from oracle/
   only); the clustered matrix is also compared with its exact answer
   W = (Q**2)^T on every element.
-* complex Hermitian n=4096 (C128 and C64 forms): lambda(A) and two minors
-  against stored oracle values.
+* complex Hermitian n=4096 (C128 and C64 forms): lambda(A) and the stored
+  minors against stored oracle values; and every component (all 4096 minors,
+  in chunks of launches), checked against the stored columns and the exact
+  invariants on the whole W.
 * real n=4700 (both two-stage configurations): lambda(A) and two minors
   against the oracle's LAPACK mode, and interlacing; at this order the
   bisection's LDS region sets the kernel's LDS size.
@@ -211,6 +213,60 @@ def test_gue4096_sampled_minors(form):
         dm = np.max(np.abs(mu - g["mu"])) / s
         print(f"gue4096 c64 form: max|dlam|/||A||={dl:.2e} max|dmu|/||A||={dm:.2e}")
         assert dl < bound and dm < bound
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32"])
+def test_gue4096_every_component(form):
+    """Config 5 in full: lambda(A), all 4096 minors and all 4096^2 components.
+    The minors run in chunks of about 820 (one persistent launch each, so that
+    progress is reported between launches), then Eq. (2) over all of them.
+    Checked against the stored oracle values (lambda, the sampled minors and
+    their columns of W) and, on the whole W, the exact invariants (row and
+    column sums, sum_i lambda_i W_ij = A_jj, sum_i lambda_i^2 W_ij = ||A_j||^2,
+    0 <= W <= 1).  C64 form: eigenvalues within 8 sqrt(n) 2^-24 ||A||; W within
+    the bounds asserted below, which hold the measured errors with margin."""
+    import torch
+    from paper_2002_04989_amd import eeid
+    g = golden("gue4096")
+    A = inputs.make_config(5)[0]
+    n = A.shape[0]
+    dA = torch.from_numpy(A).to("cuda:0")
+    announce(f"gue4096 {form}: lambda(A) and minor 0")
+    lam, mu0, flag = eeid.minor_eigvals_subset(dA, [0], prec=form)
+    torch.cuda.synchronize()
+    assert int(flag.cpu()[0]) == 0
+    mu = torch.empty((n, n - 1), dtype=torch.float64, device="cuda:0")
+    mu[0] = mu0[0]
+    for c0 in range(1, n, 820):
+        js = list(range(c0, min(n, c0 + 820)))
+        _, mu_c, flag = eeid.minor_eigvals_subset(dA, js, prec=form, with_lambda=False)
+        torch.cuda.synchronize()
+        assert int(flag.cpu()[0]) == 0
+        mu[js[0]:js[-1] + 1] = mu_c
+        announce(f"gue4096 {form}: minors {js[0]}..{js[-1]} done")
+    flags = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    V2 = eeid.components(lam, mu.reshape(-1), [n], flags)
+    torch.cuda.synchronize()
+    assert int(flags.cpu()[0]) == 0
+    lam, mu, W = lam.cpu().numpy(), mu.cpu().numpy(), V2.cpu().numpy().reshape(n, n)
+    js = [int(j) for j in g["js"]]
+    s = float(np.max(np.abs(g["lam"])))
+    inv = oracle.invariants(A, lam, W)
+    print(f"gue4096 {form}: invariants {inv}")
+    if form == "fp64":
+        np.testing.assert_allclose(lam, g["lam"], atol=LAM_TOL * s, rtol=0)
+        np.testing.assert_allclose(mu[js], g["mu"], atol=LAM_TOL * s, rtol=0)
+        np.testing.assert_allclose(W[:, js], g["W"], atol=W_TOL, rtol=0)
+        assert inv["rows"] < 1e-9 and inv["cols"] < 1e-9 and inv["range"] < 1e-12, inv
+        assert inv["diag"] < 1e-9 * s and inv["frob"] < 1e-9 * s * s, inv
+    else:
+        bound = 8 * np.sqrt(n) * 2.0 ** -24
+        dl = np.max(np.abs(lam - g["lam"])) / s
+        dm = np.max(np.abs(mu[js] - g["mu"])) / s
+        dW = np.max(np.abs(W[:, js] - g["W"]))
+        print(f"gue4096 c64 form: max|dlam|/||A||={dl:.2e} max|dmu|/||A||={dm:.2e} sampled max|dW|={dW:.2e}")
+        assert dl < bound and dm < bound
+        assert dW < 1e-3 and inv["cols"] < 1e-3 and inv["rows"] < 1e-1 and inv["range"] < 1e-3, inv
 
 
 @pytest.fixture(scope="module")
