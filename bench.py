@@ -43,7 +43,8 @@ def symv_bytes(m: int, s: int) -> int:
 
 def kernel_sources_hash() -> str:
     h = hashlib.sha256()
-    for f in ("eeid.hip", "eeid_tridiag.hpp", "eeid_tridiag_c.hpp", "eeid_band.hpp", "eeid_identity.hpp"):
+    for f in ("eeid.hip", "eeid_tridiag.hpp", "eeid_tridiag_c.hpp", "eeid_band.hpp", "eeid_identity.hpp",
+              "eeid_latency.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2002_04989_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -63,7 +64,7 @@ def kernel_name(form: str, variant: str) -> str:
 
 def measured_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed counter summary, if it matches these sources."""
-    path = os.path.join(ROOT, "profiles", "tridiag_n2048x2_counters.json")
+    path = os.path.join(ROOT, "profiles", "band_bisect_n2048x2_counters.json")
     try:
         d = json.load(open(path))
     except (OSError, ValueError):
@@ -175,7 +176,10 @@ def run_form(mats_dev, n, form, steps, warmup, tune=True):
     stream = torch.cuda.current_stream()
     res = None
     tuned = None
-    if tune:  # untimed: pick the fastest kernel configuration for this batch
+    if isinstance(tune, str):  # a configuration given on the command line
+        eeid.set_variant(tune)
+        tuned = (tune, float("nan"))
+    elif tune:  # untimed: pick the fastest kernel configuration for this batch
         tuned = eeid.autotune(mats_dev, form)
         log(f"{form}: autotune chose {tuned[0]} ({tuned[1]:.0f} ms)")
     for _ in range(warmup):
@@ -399,6 +403,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the (untimed) autotuning of kernel configurations")
     ap.add_argument("--no-paired", action="store_true", help="skip timing the paired form of the identity")
     ap.add_argument("--no-latency", action="store_true", help="skip the single-component latency table")
+    ap.add_argument("--variant", default=None, help="use this kernel configuration (eeid.VARIANTS) instead of autotuning")
     ap.add_argument("--copy-ref", action="store_true",
                     help="run a 1 GiB device copy first (reference for HBM counter scaling)")
     args = ap.parse_args()
@@ -428,8 +433,8 @@ def main():
         log("copy reference: 1 GiB read + 1 GiB write done")
 
     log(f"fp64 form: warmup {args.warmup}, steps {args.steps}")
-    res64, wall64, tri64, id64, tuned64, spread64 = run_form(mats_dev, n, "fp64", args.steps, args.warmup,
-                                                             not args.no_tune)
+    tune = args.variant if args.variant else not args.no_tune
+    res64, wall64, tri64, id64, tuned64, spread64 = run_form(mats_dev, n, "fp64", args.steps, args.warmup, tune)
     e2e64 = end_to_end_ms(mats, n, "fp64")
     comps = 2 * N * N
     ms_step = wall64 / args.steps * 1e3
@@ -469,8 +474,7 @@ def main():
     fp32 = None
     if not args.no_fp32:
         log(f"fp32 form: warmup {args.warmup}, steps {args.steps}")
-        res32, wall32, tri32, id32, tuned32, spread32 = run_form(mats_dev, n, "fp32", args.steps, args.warmup,
-                                                                 not args.no_tune)
+        res32, wall32, tri32, id32, tuned32, spread32 = run_form(mats_dev, n, "fp32", args.steps, args.warmup, tune)
         h32 = [t.cpu().numpy() for t in res32]
         variant32 = tuned32[0] if tuned32 else "nb32_nt512"
         kname32 = kernel_name("fp32", variant32)
