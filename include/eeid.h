@@ -271,6 +271,15 @@ eeid_status_t eeid_set_identity_form(eeid_handle_t h, int form);
 /* Enable (1) or disable (0) graph mode for eeid_all_components. */
 eeid_status_t eeid_set_graph_mode(eeid_handle_t h, int enable);
 
+/* Phase timers of the two-stage kernel, in builds compiled with
+ * -DEEID_PHASE_TIMERS (libeeid_phase.so; other builds return
+ * EEID_ERR_UNSUPPORTED).  ticks: host [8], the sums over all workgroups of the
+ * 100 MHz wall-clock ticks spent in 0 gather, 1 panel QR, 2 symmetric
+ * product, 3 W, 4 rank-2k update, 5 band to tridiagonal, 6 bisection,
+ * 7 queue and the rest, accumulated since the last reset (reset = 1 clears
+ * them and ignores ticks).  Synchronous; an instrument for profiling only. */
+eeid_status_t eeid_phase_ticks(unsigned long long *ticks, int reset);
+
 /* Number of compiled configurations of the real eigenvalue kernel (the
  * complex kernel has one).  Configurations 0..2 use the one-stage Householder
  * reduction, 3..4 the two-stage (dense -> band -> tridiagonal) reduction. */

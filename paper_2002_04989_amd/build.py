@@ -27,15 +27,20 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def build(force: bool = True, extra=()) -> str:
-    if not force and os.path.exists(LIB) and all(os.path.getmtime(LIB) >= os.path.getmtime(d) for d in DEPS):
-        return LIB
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, *extra, "-o", tmp, SRC]
+PHASE_LIB = os.path.join(PKG, "libeeid_phase.so")   # instrumented with per-phase timers
+
+
+def build(force: bool = True, extra=(), phase_timers: bool = False) -> str:
+    lib = PHASE_LIB if phase_timers else LIB
+    if not force and os.path.exists(lib) and all(os.path.getmtime(lib) >= os.path.getmtime(d) for d in DEPS):
+        return lib
+    tmp = lib + ".tmp"
+    flags = ["-DEEID_PHASE_TIMERS"] if phase_timers else []
+    cmd = [hipcc(), *HIPCC_FLAGS, *flags, *extra, "-o", tmp, SRC]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    print(build(force="--lazy" not in sys.argv))
+    print(build(force="--lazy" not in sys.argv, phase_timers="--phase-timers" in sys.argv))

@@ -540,6 +540,24 @@ eeid_status_t eeid_set_identity_form(eeid_handle_t h, int form) {
     return EEID_OK;
 }
 
+eeid_status_t eeid_phase_ticks(unsigned long long *ticks, int reset) {
+#ifdef EEID_PHASE_TIMERS
+    if (reset) {
+        const unsigned long long zero[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        return hipMemcpyToSymbol(HIP_SYMBOL(eeid::phase_ticks), zero, sizeof zero) == hipSuccess ? EEID_OK
+                                                                                              : EEID_ERR_HIP;
+    }
+    if (!ticks) return EEID_ERR_INVALID_ARG;
+    return hipMemcpyFromSymbol(ticks, HIP_SYMBOL(eeid::phase_ticks), 8 * sizeof(unsigned long long)) == hipSuccess
+               ? EEID_OK
+               : EEID_ERR_HIP;
+#else
+    (void)ticks;
+    (void)reset;
+    return EEID_ERR_UNSUPPORTED;
+#endif
+}
+
 int eeid_variant_count(void) { return N_REAL_VARIANTS; }
 
 eeid_status_t eeid_set_variant(eeid_handle_t h, int variant) {

@@ -59,6 +59,7 @@ struct Band {
     double *de;                        // LDS: bisection (aliases the stage-1 and chase region)
     int m, T, LD;
     int tid, lane, wave;
+    PhaseClock clk;
 
     __device__ S *tile_ptr(int I, int J) const { return tiles + tile_index(I, J, T) * TILE_ELEMS; }
     __device__ double Mget(int r, int c) const {
@@ -798,14 +799,19 @@ struct Band {
                 for (int q = tid; q < BW * BW; q += NT) Tm[q] = 0.0;
             }
             __syncthreads();
+            EEID_PHASE_MARK(clk, 4);
             panel_qr(k0);
+            EEID_PHASE_MARK(clk, 1);
             const int J1 = r0 / TILE;
             symm(J1);
             __syncthreads();
+            EEID_PHASE_MARK(clk, 2);
             make_w(J1, r0);
             __syncthreads();
+            EEID_PHASE_MARK(clk, 3);
             syr2k(J1);
             __syncthreads();
+            EEID_PHASE_MARK(clk, 4);
         }
     }
 
@@ -1192,6 +1198,7 @@ void band_bisect_kernel(TriArgs args) {
     t.red = lds + big;
     t.vec = t.red + (NT / 64) * (2 * BW + 8);
     char *slot = args.work + (int64_t)blockIdx.x * args.slot_bytes;
+    t.clk.start();
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(args.counter, 1);
         __syncthreads();
@@ -1203,6 +1210,7 @@ void band_bisect_kernel(TriArgs args) {
             for (int i = threadIdx.x; i < it.m; i += NT) it.out[i] = __builtin_nan("");
             continue;
         }
+        EEID_PHASE_MARK(t.clk, 7);
         t.m = it.m;
         t.T = (it.m + TILE - 1) / TILE;
         t.LD = t.T * TILE;
@@ -1216,13 +1224,19 @@ void band_bisect_kernel(TriArgs args) {
         t.eg = t.dg + t.LD;
         t.gather(it);
         __syncthreads();
+        EEID_PHASE_MARK(t.clk, 0);
         t.reduce_to_band();
         __syncthreads();
+        EEID_PHASE_MARK(t.clk, 4);
         t.band_to_tridiagonal(t.Tm, args.spin_limit, &args.flags[it.b]);
+        EEID_PHASE_MARK(t.clk, 5);
         t.bisect(it.out, interlacing_bracket(args, it, &s_flag));
         publish_eigenvalues(args, it);
         __syncthreads();
+        EEID_PHASE_MARK(t.clk, 6);
     }
+    EEID_PHASE_MARK(t.clk, 7);
+    t.clk.flush();
 }
 
 }  // namespace eeid

@@ -921,6 +921,40 @@ struct Tri {
     }
 };
 
+// Phase timers (built with -DEEID_PHASE_TIMERS only): thread 0 of every
+// workgroup measures each phase of each problem with the constant 100 MHz
+// wall clock and adds the ticks into phase_ticks[] once per problem.  Phases:
+// 0 gather, 1 panel QR, 2 symmetric product, 3 W, 4 rank-2k update (with the
+// panel's bookkeeping), 5 band to tridiagonal, 6 bisection (with the wait for
+// the interlacing brackets), 7 queue and the rest.  The sums over workgroups
+// divided by the resident workgroups give each phase's share of the launch.
+#ifdef EEID_PHASE_TIMERS
+__device__ unsigned long long phase_ticks[8];
+struct PhaseClock {
+    unsigned long long t = 0, acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    __device__ void start() { if (threadIdx.x == 0) t = wall_clock64(); }
+    __device__ void mark(int q) {
+        if (threadIdx.x == 0) {
+            const unsigned long long now = wall_clock64();
+            acc[q] += now - t;
+            t = now;
+        }
+    }
+    __device__ void flush() {
+        if (threadIdx.x == 0)
+            for (int q = 0; q < 8; ++q) atomicAdd(&phase_ticks[q], acc[q]);
+    }
+};
+#define EEID_PHASE_MARK(clk, q) (clk).mark(q)
+#else
+struct PhaseClock {
+    __device__ void start() {}
+    __device__ void mark(int) {}
+    __device__ void flush() {}
+};
+#define EEID_PHASE_MARK(clk, q) ((void)0)
+#endif
+
 struct TriArgs {
     const Item *items;
     int64_t n_items;

@@ -13,6 +13,7 @@ from typing import Sequence
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libeeid.so")
+PHASE_LIB_PATH = os.path.join(PKG, "libeeid_phase.so")   # the same library built with phase timers
 
 R64, C128 = 0, 1
 PREC = {"fp64": 0, "fp32": 1}
@@ -30,7 +31,7 @@ EXPORTS = (
     "eeid_set_graph_mode",
     "eeid_variant_count", "eeid_set_variant", "eeid_set_identity_form",
     "eeid_rotated_minor_eigvals", "eeid_signed_eigenvectors", "eeid_eigenvector_sq",
-    "eeid_minor_eigvals_latency",
+    "eeid_minor_eigvals_latency", "eeid_phase_ticks",
     "eeid_autotune",
 )
 VARIANTS = ("nb32_nt512", "nb32_nt256x2", "nb16_nt512", "band32_nt512", "band32_nt256x2")
@@ -77,6 +78,7 @@ def load_library(path: str = LIB_PATH):
     lib.eeid_set_identity_form.argtypes = [_vp, c]
     lib.eeid_minor_eigvals_latency.argtypes = [_vp, c, c, ctypes.c_int64, _vp, ctypes.c_int64, _i64p,
                                                _vp, _vp, _vp]
+    lib.eeid_phase_ticks.argtypes = [ctypes.POINTER(ctypes.c_ulonglong), c]
     lib.eeid_eigenvector_sq.argtypes = [_vp, ctypes.c_int64, _vp, _vp, ctypes.c_int64, _vp, _vp]
     lib.eeid_rotated_minor_eigvals.argtypes = [_vp, c, c, ctypes.c_int64, _vp, ctypes.c_int64, _vp, _vp]
     lib.eeid_signed_eigenvectors.argtypes = [_vp, ctypes.c_int64, ctypes.c_int64, _vp, _vp, _vp, _vp, _vp]
