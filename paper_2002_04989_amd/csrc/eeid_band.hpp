@@ -1147,7 +1147,7 @@ struct Band {
     }
 
     __device__ void bisect(double *out, const double *brk) {
-        bisect_tridiagonal<NT, 4>(dg, eg, m, out, de, red, tid, lane, wave, brk);
+        bisect_tridiagonal<NT, 8>(dg, eg, m, out, de, red, tid, lane, wave, brk);
     }
 };
 
