@@ -211,35 +211,38 @@ eeid_status_t eeid_components_subset(eeid_handle_t h, int64_t n, const double *l
 eeid_status_t eeid_eigenvector_sq(eeid_handle_t h, int64_t n, const double *lambda, const double *mu, int64_t i,
                                   double *row, int32_t *flag);
 
-/* Signs of the eigenvector components (Section 2: the identity applied in
- * other bases gives the directions).  For a reference index r and every
- * partner k != r, B_k = R^T A R with R the rotation by pi/4 in the (r, k)
- * plane (new basis e'_r = (e_r + e_k)/sqrt2, e'_k = (e_k - e_r)/sqrt2) has A's
- * eigenvalues, and component r of its eigenvector i is (v_ir + v_ik)/sqrt2, so
- * Eq. (2) on the minor of B_k at r gives (v_ir + v_ik)^2 / 2.
+/* Signs and phases of the eigenvector components (Section 2: the identity
+ * applied in other bases gives the directions).  For a reference index r and
+ * every partner k != r, B = R^H A R with R a rotation by pi/4 in the (r, k)
+ * plane has A's eigenvalues; with the new basis e'_r = (e_r + e_k)/sqrt2,
+ * e'_k = (e_k - e_r)/sqrt2, Eq. (2) on the minor of B at r gives
+ * (W_ir + W_ik)/2 + Re(conj(v_ir) v_ik); with e'_r = (e_r + i e_k)/sqrt2,
+ * e'_k = (e_k + i e_r)/sqrt2 (complex input only) it gives
+ * (W_ir + W_ik)/2 + Im(conj(v_ir) v_ik).
  *
- * eeid_rotated_minor_eigvals: the ascending spectra of those n - 1 minors
- * (order n - 1 each) in one persistent launch, real symmetric A (EEID_R64)
- * only (EEID_C128: EEID_ERR_UNSUPPORTED).
+ * eeid_rotated_minor_eigvals: the ascending spectra of those minors (order
+ * n - 1 each) in one persistent launch.
  *   r       0 <= r < n
- *   mu_rot  device [(n - 1) * (n - 1)] output, row q = spectrum for the q-th
- *           partner k != r in ascending order
+ *   mu_rot  device output: EEID_R64 [(n - 1) * (n - 1)], row q = the q-th
+ *           partner k != r in ascending order; EEID_C128 [2 (n - 1) * (n - 1)],
+ *           rows 0..n-2 the real rotations, rows n-1..2n-3 the imaginary ones
  *   flag    device [1] output */
 eeid_status_t eeid_rotated_minor_eigvals(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64_t n,
                                          const void *A, int64_t r, double *mu_rot, int32_t *flag);
 
-/* eeid_signed_eigenvectors: the unit eigenvectors with their signs, from
- * lambda(A) and W (as eeid_all_components writes them for this matrix) and
- * mu_rot: with S_ik the identity at r of B_k, v_ir v_ik = S_ik - (W_ir + W_ik)/2,
- * and with the sign convention v_ir >= 0,
- *   V[i * n + r] = sqrt(W_ir),  V[i * n + k] = (S_ik - (W_ir + W_ik)/2) / sqrt(W_ir).
- * Row i is the eigenvector of the i-th smallest eigenvalue.  Its absolute
- * error is about the error of W divided by sqrt(W_ir), so choose r where the
- * eigenvectors of interest are not small.  A row with W_ir = 0 has no
- * reference: it is NaN and bit 8 is OR-ed into *flag.
- *   lambda device [n], W device [n * n], mu_rot device [(n - 1)^2]
- *   V      device [n * n] output;  flag device [1] (bits OR-ed in) */
-eeid_status_t eeid_signed_eigenvectors(eeid_handle_t h, int64_t n, int64_t r, const double *lambda,
+/* eeid_signed_eigenvectors: the unit eigenvectors with their signs (phases
+ * for complex input), from lambda(A) and W (as eeid_all_components writes
+ * them for this matrix) and mu_rot: with the convention v_ir real >= 0,
+ *   V[i, r] = sqrt(W_ir),  V[i, k] = conj(v_ir) v_ik / sqrt(W_ir),
+ * conj(v_ir) v_ik taken from the rotated identities above.  Row i is the
+ * eigenvector of the i-th smallest eigenvalue; V is double [n * n] for
+ * EEID_R64 and interleaved (re, im) double [2 * n * n] for EEID_C128.  Its
+ * absolute error is about the error of W divided by sqrt(W_ir), so choose r
+ * where the eigenvectors of interest are not small.  A row with W_ir = 0 has
+ * no reference: it is NaN and bit 8 is OR-ed into *flag.
+ *   lambda device [n], W device [n * n], mu_rot device as written above
+ *   flag   device [1] (bits OR-ed in) */
+eeid_status_t eeid_signed_eigenvectors(eeid_handle_t h, eeid_dtype_t t, int64_t n, int64_t r, const double *lambda,
                                        const double *W, const double *mu_rot, double *V, int32_t *flag);
 
 /* eeid_minor_eigvals followed by eeid_components: every |v_ij|^2 of every

@@ -299,55 +299,77 @@ def components_definition(a: np.ndarray):
 # --------------------------------------------------------------------------
 def signed_eigenvectors_definition(a: np.ndarray, r: int):
     """The plain definition: (lam, V) with row i of V the unit eigenvector of
-    the i-th smallest eigenvalue of the real symmetric A, its sign fixed so
-    that V[i, r] >= 0 (a row with V[i, r] == 0 keeps the Jacobi sign)."""
-    a = hermitian_from_lower(np.asarray(a, dtype=np.float64))
+    the i-th smallest eigenvalue of the Hermitian A, its sign (real A) or phase
+    (complex A) fixed so that V[i, r] is real and >= 0 (a row with V[i, r] == 0
+    keeps the Jacobi phase)."""
+    a = hermitian_from_lower(np.asarray(a))
     w, v = eigh_jacobi(a, vectors=True)
     V = v.T.copy()
-    V[V[:, r] < 0] *= -1.0
+    ref = V[:, r]
+    mag = np.abs(ref)
+    ph = np.where(mag > 0, np.conj(ref) / np.where(mag > 0, mag, 1.0), 1.0)
+    V *= ph[:, None]
+    if not np.iscomplexobj(a):
+        V = V.real.copy()
     return w, V
 
 
-def rotation(n: int, r: int, k: int) -> np.ndarray:
-    """R with columns the basis e'_r = (e_r + e_k)/sqrt2, e'_k = (e_k - e_r)/sqrt2, e'_p = e_p otherwise."""
-    R = np.eye(n)
+def rotation(n: int, r: int, k: int, rot: int = 0) -> np.ndarray:
+    """R with columns the new basis: rot 0: e'_r = (e_r + e_k)/sqrt2, e'_k = (e_k - e_r)/sqrt2;
+    rot 1: e'_r = (e_r + i e_k)/sqrt2, e'_k = (e_k + i e_r)/sqrt2; e'_p = e_p otherwise."""
     h = 1.0 / np.sqrt(2.0)
-    R[r, r], R[k, r] = h, h
-    R[r, k], R[k, k] = -h, h
+    if rot == 0:
+        R = np.eye(n)
+        R[r, r], R[k, r] = h, h
+        R[r, k], R[k, k] = -h, h
+    else:
+        R = np.eye(n, dtype=np.complex128)
+        R[r, r], R[k, r] = h, 1j * h
+        R[r, k], R[k, k] = 1j * h, h
     return R
 
 
-def rotated_minor(a: np.ndarray, r: int, k: int) -> np.ndarray:
-    """The minor at r of B = R^T A R (R = rotation(n, r, k)): B has A's
-    eigenvalues and component r of its eigenvector i is (v_ir + v_ik)/sqrt2."""
-    a = hermitian_from_lower(np.asarray(a, dtype=np.float64))
-    R = rotation(a.shape[0], r, k)
-    return minor(R.T @ a @ R, r)
+def rotated_minor(a: np.ndarray, r: int, k: int, rot: int = 0) -> np.ndarray:
+    """The minor at r of B = R^H A R (R = rotation(n, r, k, rot)): B has A's
+    eigenvalues and component r of its eigenvector i is (v_ir + v_ik)/sqrt2
+    (rot 0) or (v_ir - i v_ik)/sqrt2 (rot 1)."""
+    a = hermitian_from_lower(np.asarray(a))
+    R = rotation(a.shape[0], r, k, rot)
+    return minor(R.conj().T @ a @ R, r)
 
 
 def signed_eigenvectors_identity(a: np.ndarray, r: int, method: str = "jacobi"):
-    """The method: signed eigenvectors from Eq. (2) in the original basis and
-    in the n - 1 rotated bases of the (r, k) planes.
+    """The method: eigenvectors with signs (phases) from Eq. (2) in the
+    original basis and in rotated bases of the (r, k) planes.
 
-    W_ik = |v_ik|^2 from the minors of A; S_ik = (v_ir + v_ik)^2 / 2 from the
-    minor at r of R^T A R (same eigenvalues, so the same denominators); then
-    v_ir v_ik = S_ik - (W_ir + W_ik) / 2, and with v_ir = sqrt(W_ir) >= 0,
-    v_ik = (S_ik - (W_ir + W_ik) / 2) / sqrt(W_ir).  Rows with W_ir = 0 are NaN.
-    Returns (lam, V) with V as in signed_eigenvectors_definition.
+    W_ik = |v_ik|^2 from the minors of A; from the minor at r of R^H A R (same
+    eigenvalues, so the same denominators) Eq. (2) gives
+    S_ik = (W_ir + W_ik)/2 + Re(conj(v_ir) v_ik) for the real rotation and, for
+    complex A, (W_ir + W_ik)/2 + Im(conj(v_ir) v_ik) for the imaginary one; with
+    v_ir = sqrt(W_ir) real >= 0, v_ik = conj(v_ir) v_ik / sqrt(W_ir).  Rows with
+    W_ir = 0 are NaN.  Returns (lam, V) with V as in signed_eigenvectors_definition.
     """
-    a = hermitian_from_lower(np.asarray(a, dtype=np.float64))
+    a = hermitian_from_lower(np.asarray(a))
+    cplx = np.iscomplexobj(a)
     n = a.shape[0]
     lam, _, W, _ = components_identity(a, method=method)
     if n == 1:
-        return lam, np.ones((1, 1))
+        return lam, np.ones((1, 1), dtype=a.dtype)
     ks = [k for k in range(n) if k != r]
-    mu_rot = np.array([eigvalsh(rotated_minor(a, r, k), method) for k in ks])
-    S, _ = identity_from_spectra(lam, mu_rot)
-    V = np.empty((n, n))
     sr = np.sqrt(W[:, r])
+    V = np.empty((n, n), dtype=np.complex128 if cplx else np.float64)
+    parts = []
+    for rot in ((0, 1) if cplx else (0,)):
+        mu_rot = np.array([eigvalsh(rotated_minor(a, r, k, rot), method) for k in ks])
+        S, _ = identity_from_spectra(lam, mu_rot)
+        parts.append(S)
     with np.errstate(divide="ignore", invalid="ignore"):
         for q, k in enumerate(ks):
-            V[:, k] = (S[:, q] - 0.5 * (W[:, r] + W[:, k])) / sr
+            half = 0.5 * (W[:, r] + W[:, k])
+            val = parts[0][:, q] - half
+            if cplx:
+                val = val + 1j * (parts[1][:, q] - half)
+            V[:, k] = val / sr
     V[:, r] = sr
     V[W[:, r] == 0.0] = np.nan
     return lam, V

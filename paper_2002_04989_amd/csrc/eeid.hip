@@ -261,11 +261,14 @@ eeid_status_t prepare_eigs(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64
         if (kind == 2 && nb >= 2)
             for (int64_t q = 0; q < nsel; ++q)
                 items.push_back(Item{src, mu + q * (nb - 1), nb, (int)js[q], nb - 1, (int32_t)b, -1, 0});
-        // kind 3: minors at js[0] of the rotated matrices R^T A R, one per partner k != js[0]
+        // kind 3: minors at js[0] of the rotated matrices R^H A R, one per partner k != js[0]
+        // (complex input: the real rotations, then the imaginary ones)
         if (kind == 3 && nb >= 2)
-            for (int k = 0, q = 0; k < nb; ++k)
-                if (k != (int)js[0])
-                    items.push_back(Item{src, mu + (int64_t)(q++) * (nb - 1), nb, (int)js[0], nb - 1, (int32_t)b, k, 0});
+            for (int rot = 0, q = 0; rot < (t == EEID_C128 ? 2 : 1); ++rot)
+                for (int k = 0; k < nb; ++k)
+                    if (k != (int)js[0])
+                        items.push_back(
+                            Item{src, mu + (int64_t)(q++) * (nb - 1), nb, (int)js[0], nb - 1, (int32_t)b, k, rot});
         lam += nb;
         muo += (int64_t)nb * (nb - 1);
     }
@@ -279,7 +282,7 @@ eeid_status_t prepare_eigs(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64
         ikey.push_back((int64_t)(intptr_t)it.out);
         ikey.push_back(((int64_t)it.n << 32) | (uint32_t)it.j);
         ikey.push_back(((int64_t)it.m << 32) | (uint32_t)it.b);
-        ikey.push_back(it.k);
+        ikey.push_back(((int64_t)it.k << 32) | (uint32_t)it.rot);
     }
     s = upload_table(h, h->items, h->items_key, ikey, items);
     if (s != EEID_OK) return s;
@@ -795,7 +798,6 @@ eeid_status_t eeid_rotated_minor_eigvals(eeid_handle_t h, eeid_dtype_t t, eeid_p
     const int64_t zero = 0;
     eeid_status_t s = check_batch(h, t, p, 1, &n, &zero, A);
     if (s != EEID_OK) return s;
-    if (t != EEID_R64) return fail(h, EEID_ERR_UNSUPPORTED, "rotated minors: real symmetric input only");
     if (r < 0 || r >= n) return fail(h, EEID_ERR_INVALID_ARG, "reference index r out of range");
     if (!flag) return fail(h, EEID_ERR_INVALID_ARG, "null flag pointer");
     if (n >= 2 && !mu_rot) return fail(h, EEID_ERR_INVALID_ARG, "mu_rot is null");
@@ -804,10 +806,13 @@ eeid_status_t eeid_rotated_minor_eigvals(eeid_handle_t h, eeid_dtype_t t, eeid_p
     return s != EEID_OK ? s : run_now(h, e);
 }
 
-eeid_status_t eeid_signed_eigenvectors(eeid_handle_t h, int64_t n, int64_t r, const double *lambda, const double *W,
-                                       const double *mu_rot, double *V, int32_t *flag) {
+eeid_status_t eeid_signed_eigenvectors(eeid_handle_t h, eeid_dtype_t t, int64_t n, int64_t r, const double *lambda,
+                                       const double *W, const double *mu_rot, double *V, int32_t *flag) {
     if (!h) return EEID_ERR_INVALID_ARG;
-    if (n < 1 || n > EEID_MAX_N_R64) return fail(h, EEID_ERR_INVALID_ARG, "n out of range");
+    if (t != EEID_R64 && t != EEID_C128) return fail(h, EEID_ERR_INVALID_ARG, "unknown dtype");
+    if (n < 1 || n > (t == EEID_R64 ? EEID_MAX_N_R64 : EEID_MAX_N_C128))
+        return fail(h, EEID_ERR_INVALID_ARG, "n out of range");
+    const int64_t fam = (t == EEID_C128) ? 2 : 1;   // rotated families: real, and imaginary for complex input
     if (r < 0 || r >= n) return fail(h, EEID_ERR_INVALID_ARG, "reference index r out of range");
     if (!lambda || !W || !V || !flag || (n >= 2 && !mu_rot))
         return fail(h, EEID_ERR_INVALID_ARG, "null pointer argument");
@@ -816,18 +821,22 @@ eeid_status_t eeid_signed_eigenvectors(eeid_handle_t h, int64_t n, int64_t r, co
     Enqueue e;
     if (n >= 2) {
         const int64_t zero = 0;
-        eeid_status_t s = upload_desc(h, h->desc_sub, h->desc_sub_key, 1, &n, &zero, n - 1);
+        eeid_status_t s = upload_desc(h, h->desc_sub, h->desc_sub_key, 1, &n, &zero, fam * (n - 1));
         if (s != EEID_OK) return s;
-        s = ensure(h, h->sbuf, sizeof(double) * (size_t)(n * (n - 1)));
+        s = ensure(h, h->sbuf, sizeof(double) * (size_t)(n * fam * (n - 1)));
         if (s != EEID_OK) return s;
         S = reinterpret_cast<double *>(h->sbuf.p);
-        s = prepare_identity(h, h->desc_sub, h->dpair_sub, 1, n, n - 1, n, lambda, mu_rot, S, flag, &e);
+        s = prepare_identity(h, h->desc_sub, h->dpair_sub, 1, n, fam * (n - 1), n, lambda, mu_rot, S, flag, &e);
         if (s != EEID_OK) return s;
         s = run_now(h, e);
         if (s != EEID_OK) return s;
     }
-    hipLaunchKernelGGL(eeid::signed_vectors_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)n), dim3(256), 0,
-                       h->stream, (int)n, (int)r, W, S, V, flag);
+    if (fam == 2)
+        hipLaunchKernelGGL(eeid::signed_vectors_kernel<true>, dim3((unsigned)((n + 255) / 256), (unsigned)n),
+                           dim3(256), 0, h->stream, (int)n, (int)r, W, S, V, flag);
+    else
+        hipLaunchKernelGGL(eeid::signed_vectors_kernel<false>, dim3((unsigned)((n + 255) / 256), (unsigned)n),
+                           dim3(256), 0, h->stream, (int)n, (int)r, W, S, V, flag);
     HIP_TRY(h, hipGetLastError());
     return EEID_OK;
 }

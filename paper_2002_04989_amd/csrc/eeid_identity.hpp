@@ -219,32 +219,44 @@ __global__ __launch_bounds__(256) void identity_kernel(const BatchDesc *desc, co
     }
 }
 
-// Signed eigenvectors from Eq. (2) in the original basis and in the n - 1
+// Signed (or phased) eigenvectors from Eq. (2) in the original basis and in
 // rotated bases of the (r, k) planes (Section 2: the identity applied in other
 // bases gives the directions).  W_ik = |v_ik|^2 (row-major, n x n); S holds,
-// for the q-th partner k != r (ascending), S[i (n-1) + q] = (v_ir + v_ik)^2 / 2,
-// the identity at r of the rotated matrix.  Then v_ir v_ik =
-// S_ik - (W_ir + W_ik) / 2 and, with the sign convention v_ir >= 0,
-// V[i n + k] = (S_ik - (W_ir + W_ik) / 2) / sqrt(W_ir), V[i n + r] = sqrt(W_ir).
-// A row with W_ir = 0 has no sign reference: it is NaN and flag bit 8 is set.
+// per row i, the identity at r of the rotated matrices: column q (the q-th
+// partner k != r, ascending) = (W_ir + W_ik)/2 + Re(conj(v_ir) v_ik), and for
+// complex input column n - 1 + q = (W_ir + W_ik)/2 + Im(conj(v_ir) v_ik).
+// With the convention v_ir real >= 0:
+//   V[i, r] = sqrt(W_ir),  V[i, k] = conj(v_ir) v_ik / sqrt(W_ir),
+// real (CPLX false) or interleaved (re, im) (CPLX true).  A row with W_ir = 0
+// has no reference: it is NaN and flag bit 8 is set.
+template <bool CPLX>
 __global__ __launch_bounds__(256) void signed_vectors_kernel(int n, int r, const double *W, const double *S,
                                                               double *V, int32_t *flag) {
     const int i = blockIdx.y;
     const int k = blockIdx.x * 256 + threadIdx.x;
     if (k >= n) return;
+    const int fam = CPLX ? 2 : 1;
     const double wr = W[(int64_t)i * n + r];
     const double sr = sqrt(wr);
-    double v;
+    double re, im = 0.0;
     if (!(wr > 0.0)) {
-        v = __builtin_nan("");
+        re = im = __builtin_nan("");
         if (k == 0) atomicOr(flag, 8);
     } else if (k == r) {
-        v = sr;
+        re = sr;
     } else {
         const int q = k - (k > r ? 1 : 0);
-        v = (S[(int64_t)i * (n - 1) + q] - 0.5 * (wr + W[(int64_t)i * n + k])) / sr;
+        const double half = 0.5 * (wr + W[(int64_t)i * n + k]);
+        const double *Si = S + (int64_t)i * fam * (n - 1);
+        re = (Si[q] - half) / sr;
+        if (CPLX) im = (Si[n - 1 + q] - half) / sr;
     }
-    V[(int64_t)i * n + k] = v;
+    if (CPLX) {
+        V[2 * ((int64_t)i * n + k)] = re;
+        V[2 * ((int64_t)i * n + k) + 1] = im;
+    } else {
+        V[(int64_t)i * n + k] = re;
+    }
 }
 
 // Eq. (2) in the paired form of Algorithm 2 (Section 3): with lambda_i taken

@@ -42,8 +42,8 @@ struct Item {
     int32_t j;          // deleted row/column, -1 for the matrix itself
     int32_t m;          // order of the problem (n or n - 1)
     int32_t b;          // batch index (flags)
-    int32_t k;          // >= 0: the minor is taken of R^T A R, R the pi/4 rotation in the (j, k) plane
-    int32_t pad;
+    int32_t k;          // >= 0: the minor is taken of R^H A R, R a pi/4 rotation in the (j, k) plane
+    int32_t rot;        // the rotation: 0 real (e_j + e_k)/sqrt2, 1 imaginary (e_j + i e_k)/sqrt2 (complex input)
 };
 
 // Element (p, q) of the symmetric matrix whose lower triangle is A (row-major, order n).

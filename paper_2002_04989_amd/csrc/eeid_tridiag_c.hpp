@@ -45,6 +45,39 @@ __device__ __forceinline__ cd cfmac(cd a, cd b, cd s) {
 __device__ __forceinline__ cd cselect(bool c, cd a, cd b) { return cd{c ? a.re : b.re, c ? a.im : b.im}; }
 __device__ __forceinline__ cd cshfl(cd a, int src) { return cd{__shfl(a.re, src), __shfl(a.im, src)}; }
 
+// Element (p, q) of the Hermitian matrix whose lower triangle is A
+// (interleaved (re, im), row-major, order n); the diagonal's imaginary part is ignored.
+__device__ __forceinline__ cd herm_at(const double *A, int n, int p, int q) {
+    if (p > q) return cd{A[2 * ((int64_t)p * n + q)], A[2 * ((int64_t)p * n + q) + 1]};
+    if (p < q) return cd{A[2 * ((int64_t)q * n + p)], -A[2 * ((int64_t)q * n + p) + 1]};
+    return cd{A[2 * ((int64_t)p * n + p)], 0.0};
+}
+
+// Element (p, q), p, q != r, of B = R^H A R with R a rotation by pi/4 in the
+// (r, k) plane.  rot 0: new basis e'_r = (e_r + e_k)/sqrt2, e'_k = (e_k - e_r)/sqrt2,
+// so component r of eigenvector i of B is (v_ir + v_ik)/sqrt2 and Eq. (2) at r
+// gives (W_ir + W_ik)/2 + Re(conj(v_ir) v_ik); rot 1: e'_r = (e_r + i e_k)/sqrt2,
+// e'_k = (e_k + i e_r)/sqrt2, component r is (v_ir - i v_ik)/sqrt2 and Eq. (2)
+// gives (W_ir + W_ik)/2 + Im(conj(v_ir) v_ik).  Only row and column k of the
+// minor at r differ from A's.
+__device__ __forceinline__ cd herm_rotated_at(const double *A, int n, int r, int k, int rot, int p, int q) {
+    constexpr double h = 0.70710678118654752440;   // 1/sqrt2
+    if (p == k && q == k) {
+        const cd akr = herm_at(A, n, k, r);
+        const double dd = herm_at(A, n, k, k).re + herm_at(A, n, r, r).re;
+        return cd{rot ? 0.5 * dd - akr.im : 0.5 * dd - akr.re, 0.0};
+    }
+    if (p == k) {   // e'_k^H A e_q
+        const cd a = herm_at(A, n, k, q), b = herm_at(A, n, r, q);
+        return rot ? cd{h * (a.re + b.im), h * (a.im - b.re)} : cd{h * (a.re - b.re), h * (a.im - b.im)};
+    }
+    if (q == k) {   // e_p^H A e'_k = conj(e'_k^H A e_p)
+        const cd a = herm_at(A, n, p, k), b = herm_at(A, n, p, r);
+        return rot ? cd{h * (a.re - b.im), h * (a.im + b.re)} : cd{h * (a.re - b.re), h * (a.im - b.im)};
+    }
+    return herm_at(A, n, p, q);
+}
+
 template <class R> struct CVec;
 template <> struct CVec<double> { static constexpr int CV = 1; typedef double2 type; };
 template <> struct CVec<float> { static constexpr int CV = 2; typedef float4 type; };
@@ -101,15 +134,9 @@ struct TriC {
                     if (row < m && col < m) {
                         const int rs = row + ((j >= 0 && row >= j) ? 1 : 0);
                         const int cs = col + ((j >= 0 && col >= j) ? 1 : 0);
-                        if (rs > cs) {
-                            vr = A[2 * ((int64_t)rs * n + cs)];
-                            vi = A[2 * ((int64_t)rs * n + cs) + 1];
-                        } else if (rs < cs) {
-                            vr = A[2 * ((int64_t)cs * n + rs)];
-                            vi = -A[2 * ((int64_t)cs * n + rs) + 1];
-                        } else {
-                            vr = A[2 * ((int64_t)rs * n + rs)];
-                        }
+                        const cd v = (it.k >= 0) ? herm_rotated_at(A, n, j, it.k, it.rot, rs, cs) : herm_at(A, n, rs, cs);
+                        vr = v.re;
+                        vi = v.im;
                     }
                     tp[2 * q] = (R)vr;
                     tp[2 * q + 1] = (R)vi;

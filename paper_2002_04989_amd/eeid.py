@@ -81,7 +81,7 @@ def load_library(path: str = LIB_PATH):
     lib.eeid_phase_ticks.argtypes = [ctypes.POINTER(ctypes.c_ulonglong), c]
     lib.eeid_eigenvector_sq.argtypes = [_vp, ctypes.c_int64, _vp, _vp, ctypes.c_int64, _vp, _vp]
     lib.eeid_rotated_minor_eigvals.argtypes = [_vp, c, c, ctypes.c_int64, _vp, ctypes.c_int64, _vp, _vp]
-    lib.eeid_signed_eigenvectors.argtypes = [_vp, ctypes.c_int64, ctypes.c_int64, _vp, _vp, _vp, _vp, _vp]
+    lib.eeid_signed_eigenvectors.argtypes = [_vp, c, ctypes.c_int64, ctypes.c_int64, _vp, _vp, _vp, _vp, _vp]
     lib.eeid_variant_count.argtypes = []
     lib.eeid_variant_count.restype = c
     lib.eeid_set_variant.argtypes = [_vp, c]
@@ -342,24 +342,27 @@ def rotated_minor_eigvals(A, r: int, prec: str = "fp64"):
         raise ValueError("A must be a square GPU tensor")
     A = A.contiguous()
     n = int(A.shape[0])
-    mu_rot = torch.empty((max(n - 1, 1), max(n - 1, 1)), dtype=torch.float64, device=A.device)
+    fam = 2 if _dtype_code(A) == C128 else 1
+    mu_rot = torch.empty((max(fam * (n - 1), 1), max(n - 1, 1)), dtype=torch.float64, device=A.device)
     flag = torch.empty(1, dtype=torch.int32, device=A.device)
     h = handle(A.device.index)
     _check(load_library().eeid_rotated_minor_eigvals(h, _dtype_code(A), PREC[prec], n, A.data_ptr(), int(r),
                                                       mu_rot.data_ptr(), flag.data_ptr()), h)
-    return mu_rot[:n - 1, :n - 1], flag
+    return mu_rot[:fam * (n - 1), :n - 1], flag
 
 
 def signed_eigenvectors(A, r: int = 0, prec: str = "fp64"):
-    """Unit eigenvectors with signs (v_ir >= 0) from Eq. (2) in the original and
-    the rotated bases: (lambda, V [n, n] with row i the i-th eigenvector, flags)."""
+    """Unit eigenvectors with signs (phases for complex A; v_ir real >= 0) from
+    Eq. (2) in the original and the rotated bases: (lambda, V [n, n] with row i
+    the i-th eigenvector, float64 or complex128 like A, flags)."""
     import torch
     n = int(A.shape[0])
+    t = _dtype_code(A)
     lam, mu, V2, flags = all_components(A, prec)
     mu_rot, flag_rot = rotated_minor_eigvals(A, r, prec)
-    V = torch.empty((n, n), dtype=torch.float64, device=A.device)
+    V = torch.empty((n, n), dtype=torch.complex128 if t == C128 else torch.float64, device=A.device)
     h = handle(A.device.index)
-    _check(load_library().eeid_signed_eigenvectors(h, n, int(r), lam.data_ptr(), V2.data_ptr(),
+    _check(load_library().eeid_signed_eigenvectors(h, t, n, int(r), lam.data_ptr(), V2.data_ptr(),
                                                     mu_rot.data_ptr() if n > 1 else None, V.data_ptr(),
                                                     flags.data_ptr()), h)
     return lam, V, flags | flag_rot

@@ -11,7 +11,10 @@ and against closed forms:
   oracle's rotated_minor on sampled partners; the result is orthonormal.
 * the discrete Laplacian: sine eigenvectors with their signs; a reference
   index where some eigenvector vanishes gives that row NaN and flag 8.
-* complex input is refused (EEID_ERR_UNSUPPORTED).
+* complex Hermitian input: phases (v_ir real >= 0) from the real and the
+  imaginary rotations, against the definition on GUE sizes, the closed form
+  D L D^H (unitarily rotated Laplacian), both rotated families' spectra
+  against the oracle, and the C64 form's bound.
 """
 import numpy as np
 import pytest
@@ -40,12 +43,12 @@ def gpu_signed(A, r, prec="fp64", variant=None):
 
 def check_against_definition(A, r, V, tol_w=1e-11):
     _, Vd = oracle.signed_eigenvectors_definition(A, r)
-    wr = Vd[:, r] ** 2
+    wr = np.abs(Vd[:, r]) ** 2
     ok = wr > 1e-8
     err = np.abs(V[ok] - Vd[ok]).max(axis=1)
     bound = tol_w / np.sqrt(wr[ok]) + 1e-12
     assert np.all(err <= bound), (np.max(err / bound), int(np.argmax(err / bound)))
-    G = V[ok] @ V[ok].T
+    G = V[ok] @ V[ok].conj().T
     assert np.max(np.abs(G - np.eye(len(G)))) < 1e-9
 
 
@@ -115,10 +118,57 @@ def test_fp32_form_signs():
     assert err < 1e-3
 
 
-def test_complex_is_refused():
+@pytest.mark.parametrize("n", [2, 3, 17, 65, 130])
+def test_gue_phased_eigenvectors(n):
+    A = inputs.gue(n, 800 + n)
+    r = n // 2
+    announce(f"phased eigenvectors GUE n={n} r={r}")
+    lam, V, flag = gpu_signed(A, r)
+    assert flag == 0 and V.dtype == np.complex128
+    check_against_definition(A, r, V, tol_w=1e-11 * max(1, n / 64))
+
+
+def test_complex_rotated_minor_spectra():
     import torch
     from paper_2002_04989_amd import eeid
-    A = torch.from_numpy(inputs.gue(8, 1)).to("cuda:0")
-    with pytest.raises(eeid.EEIDError) as e:
-        eeid.rotated_minor_eigvals(A, 0)
-    assert e.value.status == 5
+    n, r = 70, 33
+    A = inputs.gue(n, 21)
+    announce(f"complex rotated minors n={n} r={r}")
+    mu_rot, flag = eeid.rotated_minor_eigvals(torch.from_numpy(A).to("cuda:0"), r)
+    torch.cuda.synchronize()
+    mu_rot = mu_rot.cpu().numpy()
+    assert int(flag.cpu()[0]) == 0 and mu_rot.shape == (2 * (n - 1), n - 1)
+    s = norm2(A)
+    ks = [k for k in range(n) if k != r]
+    for rot in (0, 1):
+        for q in (0, 32, 33, 68):
+            mu_o = oracle.eigvalsh(oracle.rotated_minor(A, r, ks[q], rot))
+            np.testing.assert_allclose(mu_rot[rot * (n - 1) + q], mu_o, atol=1e-10 * s, rtol=0)
+
+
+def test_rotated_laplacian_phases_closed_form():
+    n, r = 64, 5
+    announce(f"phased eigenvectors of D L D^H, n={n}")
+    theta = np.random.default_rng(3).uniform(-np.pi, np.pi, n)
+    D = np.exp(1j * theta)
+    L = 2 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)
+    Ap = np.ascontiguousarray((D[:, None] * L) * np.conj(D)[None, :])
+    k = np.arange(1, n + 1)
+    Vs = np.sqrt(2.0 / (n + 1)) * np.sin(np.outer(k, k) * np.pi / (n + 1))
+    Vx = Vs * np.exp(1j * (theta[None, :] - theta[r])) * np.sign(Vs[:, r])[:, None]
+    lam, V, flag = gpu_signed(Ap, r)
+    assert flag == 0
+    np.testing.assert_allclose(lam, 2 - 2 * np.cos(k * np.pi / (n + 1)), atol=1e-13)
+    assert np.max(np.abs(V - Vx)) < 1e-10
+
+
+def test_c64_form_phases():
+    n, r = 120, 7
+    A = inputs.gue(n, 19)
+    announce(f"phased eigenvectors c64 form n={n}")
+    _, V, flag = gpu_signed(A, r, "fp32")
+    _, Vd = oracle.signed_eigenvectors_definition(A, r)
+    ok = np.abs(Vd[:, r]) ** 2 > 1e-3
+    err = np.max(np.abs(V[ok] - Vd[ok]))
+    print(f"c64 form: max phase-recovered vector error {err:.2e} on {ok.sum()} rows")
+    assert err < 1e-3

@@ -349,3 +349,67 @@ def test_rotated_minor_is_the_minor_of_a_similar_matrix():
         # Eq. (2) at r on the rotated matrix gives (v_ir + v_ik)^2 / 2
         S, _ = oracle.identity_from_spectra(lam, mu[None, :])
         np.testing.assert_allclose(S[:, 0], 0.5 * (V[:, 2] + V[:, k]) ** 2, atol=1e-12)
+
+
+@pytest.mark.parametrize("n, r", [(2, 0), (9, 0), (9, 3), (33, 10)])
+def test_phased_eigenvectors_of_a_unitarily_rotated_laplacian(n, r):
+    # A' = D L D^H with D = diag(exp(i theta)) has eigenvectors D v (v the sine
+    # vectors); fixing component r real >= 0 gives exp(i (theta_k - theta_r)) v_k sign(v_r)
+    theta = np.random.default_rng(n + r).uniform(-np.pi, np.pi, n)
+    D = np.exp(1j * theta)
+    L = 2 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)
+    Ap = (D[:, None] * L) * np.conj(D)[None, :]
+    Vs = laplacian_vectors(n)
+    Vx = Vs * np.exp(1j * (theta[None, :] - theta[r])) * np.sign(Vs[:, r])[:, None]
+    zero_ref = np.abs(Vs[:, r]) < 1e-12
+    _, Vd = oracle.signed_eigenvectors_definition(Ap, r)
+    assert np.max(np.abs(Vd[~zero_ref] - Vx[~zero_ref])) < 1e-13
+    _, Vi = oracle.signed_eigenvectors_identity(Ap, r)
+    assert np.all(np.isnan(Vi[zero_ref])) and not np.any(np.isnan(Vi[~zero_ref]))
+    assert np.max(np.abs(Vi[~zero_ref] - Vx[~zero_ref])) < 1e-12
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_phased_eigenvectors_hermitian_2x2_closed_form(seed):
+    r = np.random.default_rng(50 + seed)
+    a, c = r.standard_normal(2)
+    b = r.standard_normal() + 1j * r.standard_normal()
+    A = np.array([[a, np.conj(b)], [b, c]])
+    lam, _ = closed_2x2(a, b, c)
+    for ref in (0, 1):
+        # (A - lambda) v = 0: first row a v0 + conj(b) v1 = lambda v0, so v = (conj(b), lambda - a)
+        Vx = np.array([[np.conj(b), l - a] for l in lam])
+        Vx /= np.linalg.norm(Vx, axis=1)[:, None]
+        Vx *= (np.conj(Vx[:, ref]) / np.abs(Vx[:, ref]))[:, None]
+        _, Vd = oracle.signed_eigenvectors_definition(A, ref)
+        _, Vi = oracle.signed_eigenvectors_identity(A, ref)
+        assert np.max(np.abs(Vd - Vx)) < 1e-13 and np.max(np.abs(Vi - Vx)) < 1e-12
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_phased_eigenvectors_method_matches_definition_tiny(seed):
+    r = np.random.default_rng(2000 + seed)
+    n = int(r.integers(2, 8))
+    G = r.standard_normal((n, n)) + 1j * r.standard_normal((n, n))
+    A = (G + G.conj().T) / 2
+    ref = int(r.integers(0, n))
+    _, Vd = oracle.signed_eigenvectors_definition(A, ref)
+    _, Vi = oracle.signed_eigenvectors_identity(A, ref)
+    ok = np.abs(Vd[:, ref]) ** 2 > 1e-6
+    assert np.max(np.abs(Vi[ok] - Vd[ok])) < 1e-10
+
+
+def test_complex_rotated_minors_give_real_and_imaginary_parts():
+    A = inputs.gue(10, 7)
+    lam = oracle.eigvalsh(A)
+    _, V = oracle.signed_eigenvectors_definition(A, 4)
+    W = np.abs(V) ** 2
+    for k in (0, 5, 9):
+        for rot, part in ((0, np.real), (1, np.imag)):
+            R = O.rotation(10, 4, k, rot)
+            np.testing.assert_allclose(R.conj().T @ R, np.eye(10), atol=1e-15)
+            mu = oracle.eigvalsh(oracle.rotated_minor(A, 4, k, rot))
+            assert np.all(lam[:-1] <= mu + 1e-13) and np.all(mu <= lam[1:] + 1e-13)
+            S, _ = oracle.identity_from_spectra(lam, mu[None, :])
+            expect = 0.5 * (W[:, 4] + W[:, k]) + part(np.conj(V[:, 4]) * V[:, k])
+            np.testing.assert_allclose(S[:, 0], expect, atol=1e-12)
