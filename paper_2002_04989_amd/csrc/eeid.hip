@@ -321,7 +321,6 @@ eeid_status_t prepare_eigs(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64
     a.slot_bytes = kc.slot;
     a.LDmax = LDmax;
     a.spin_limit = h->spin_limit;
-    a.wait_lambda = (lambda != nullptr) ? 1 : 0;
     const eeid::BatchDesc *desc = reinterpret_cast<const eeid::BatchDesc *>(h->desc.p);
     const unsigned nn_blocks = (unsigned)((nmax * nmax + 4095) / 4096);
     const int cplx = (t == EEID_C128) ? 1 : 0;

@@ -1149,6 +1149,89 @@ struct Band {
     __device__ void bisect(double *out, const double *brk) {
         bisect_tridiagonal<NT, 8>(dg, eg, m, out, de, red, tid, lane, wave, brk);
     }
+
+    // ------------------------------------------------- small orders, in LDS
+    // m <= SMALL_MAX: the problem lives in LDS as a packed lower triangle
+    // (column c at c (2m - c + 1) / 2, rows c..m-1) and is reduced by unblocked
+    // Householder steps -- per column the norm, the reflector (beta real),
+    // y = A u, w = tau y - (tau^2 / 2)(u^T y) u and A -= u w^T + w u^T on the
+    // trailing triangle, with every reduction over the waves in a fixed order
+    // -- then bisected like the large problems.  No HBM traffic but the
+    // gather; the two-stage path's panels, tiles and chase are latency there.
+    static constexpr int SMALL_MAX = 128;
+    __device__ __forceinline__ int pk(int r, int c) const { return c * (2 * m - c + 1) / 2 + (r - c); }
+
+    __device__ void small_tridiagonal(const Item &it, double *L) {
+        double *u = L + SMALL_MAX * (SMALL_MAX + 1) / 2;
+        double *yw = u + SMALL_MAX;
+        double *ds = yw + SMALL_MAX, *es = ds + SMALL_MAX;
+        const int n = it.n, j = it.j;
+        // thread per row r, its entries (r, 0..r)
+        for (int r = tid; r < m; r += NT) {
+            const int rs = r + ((j >= 0 && r >= j) ? 1 : 0);
+            for (int c = 0; c <= r; ++c) {
+                const int cs = c + ((j >= 0 && c >= j) ? 1 : 0);
+                L[pk(r, c)] = (it.k >= 0) ? rotated_at(it.src, n, j, it.k, rs, cs) : lower_at(it.src, n, rs, cs);
+            }
+        }
+        __syncthreads();
+        for (int k = 0; k + 2 < m; ++k) {
+            const int t0 = k + 1;
+            // sigma^2 = sum_{i > k+1} L(i, k)^2: one wave, fixed tree
+            if (wave == 0) {
+                double sg = 0.0;
+                for (int i = k + 2 + lane; i < m; i += 64) { const double x = L[pk(i, k)]; sg = fma(x, x, sg); }
+                sg = wave_sum(sg);
+                if (lane == 0) red[0] = sg;
+            }
+            __syncthreads();
+            const double sg = red[0];
+            const double alpha = L[pk(t0, k)];
+            double tau = 0.0, scal = 0.0, beta = alpha;
+            if (sg != 0.0) {
+                const double nrm = sqrt(fma(alpha, alpha, sg));
+                beta = (alpha >= 0.0) ? -nrm : nrm;
+                tau = (beta - alpha) / beta;
+                scal = 1.0 / (alpha - beta);
+            }
+            if (tid == 0) { ds[k] = L[pk(k, k)]; es[k] = beta; }
+            if (tau == 0.0) { __syncthreads(); continue; }
+            for (int i = t0 + tid; i < m; i += NT) u[i] = (i == t0) ? 1.0 : L[pk(i, k)] * scal;
+            __syncthreads();
+            // y = A22 u (thread per row) and the per-wave parts of u^T y
+            double part = 0.0;
+            for (int i = t0 + tid; i < m; i += NT) {
+                double y = 0.0;
+                for (int c = t0; c < m; ++c) y = fma((c <= i) ? L[pk(i, c)] : L[pk(c, i)], u[c], y);
+                yw[i] = y;
+                part = fma(u[i], y, part);
+            }
+            part = wave_sum(part);
+            if (lane == 0) red[8 + wave] = part;
+            __syncthreads();
+            double uy = 0.0;
+            for (int w = 0; w < NWAVE; ++w) uy += red[8 + w];
+            const double kap = 0.5 * tau * tau * uy;
+            for (int i = t0 + tid; i < m; i += NT) yw[i] = fma(-kap, u[i], tau * yw[i]);   // y -> w
+            __syncthreads();
+            // A22 -= u w^T + w u^T on the packed trailing triangle, thread per row
+            for (int r = t0 + tid; r < m; r += NT) {
+                const double ur = u[r], wr = yw[r];
+                for (int c = t0; c <= r; ++c) L[pk(r, c)] -= fma(ur, yw[c], wr * u[c]);
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            if (m >= 2) {
+                ds[m - 2] = L[pk(m - 2, m - 2)];
+                es[m - 2] = L[pk(m - 1, m - 2)];
+            }
+            ds[m - 1] = L[pk(m - 1, m - 1)];
+        }
+        __syncthreads();
+        dg = ds;
+        eg = es;
+    }
 };
 
 template <class S>
@@ -1173,6 +1256,11 @@ __host__ __device__ inline int64_t lds_big_band(int LDmax) {
     const int64_t bis = 2 * (int64_t)LDmax;
     return (stage1 > chase ? (stage1 > bis ? stage1 : bis) : (chase > bis ? chase : bis));
 }
+
+// The small-order path keeps a packed triangle of order 128 and five vectors in
+// the same region (the chase's share alone is larger for every configuration).
+static_assert((4 * (6 * BW + 2 * 40 + 2 * 16 * 64)) >= 128 * 129 / 2 + 4 * 128 + 2 * 128,
+              "LDS region too small for the small-order path");
 
 template <int NT>
 __host__ __device__ inline int64_t lds_bytes_band(int LDmax) {
@@ -1222,6 +1310,18 @@ void band_bisect_kernel(TriArgs args) {
         t.bnd = t.Wm + (int64_t)BW * t.LD;
         t.dg = t.bnd + (int64_t)BLD * (t.LD + BW);
         t.eg = t.dg + t.LD;
+        if (it.m <= Band<S, NT>::SMALL_MAX) {
+            // small order: reduced in LDS (the slot's d and e are not used)
+            t.small_tridiagonal(it, lds);
+            EEID_PHASE_MARK(t.clk, 5);
+            t.de = t.dg + 2 * Band<S, NT>::SMALL_MAX;   // the (d, e^2) pairs after d and e, in LDS
+            t.bisect(it.out, interlacing_bracket(args, it, &s_flag));
+            t.de = lds;
+            publish_eigenvalues(args, it);
+            __syncthreads();
+            EEID_PHASE_MARK(t.clk, 6);
+            continue;
+        }
         t.gather(it);
         __syncthreads();
         EEID_PHASE_MARK(t.clk, 0);

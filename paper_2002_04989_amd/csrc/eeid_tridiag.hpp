@@ -258,9 +258,9 @@ struct Panel {
 // counts: count(x) = #{i : q_i < 0}, q_0 = d_0 - x, q_i = d_i - x - e_{i-1}^2 / q_{i-1},
 // tiny pivots replaced by -pivmin.  Bisection from a widened Gershgorin
 // interval stops at ulp level (relative 2 eps, absolute eps ||T||), at most
-// 80 halvings.  One lane per eigenvalue, ILP eigenvalues per lane in
-// lockstep; de (LDS, >= 2m doubles) receives (d_i, e_{i-1}^2) pairs, red
-// (LDS) the workgroup reductions.
+// 80 halvings.  One lane per eigenvalue, up to ILP eigenvalues per lane in
+// lockstep (fewer when the block holds fewer eigenvalues); de (LDS, >= 2m
+// doubles) receives (d_i, e_{i-1}^2) pairs, red (LDS) the workgroup reductions.
 //
 // Two forms of the count.  With every operation correctly rounded (IEEE
 // division) the computed count is monotone in x, which makes bisection
@@ -274,11 +274,158 @@ struct Panel {
 // halvings bring it back to the stopping width.  Every returned eigenvalue
 // therefore comes from a bracket certified by the monotone count.
 //
+// i_begin, i_end: only eigenvalues i_begin .. i_end - 1 are computed (the
+// workgroup's share when several share one tridiagonal); default all.
+//
 // brk (optional): the m + 1 ascending eigenvalues of a matrix of which T is
 // similar to a principal minor.  By Cauchy interlacing eigenvalue k of the
-// minor lies in [brk[k], brk[k + 1]]; that interval, widened by the rounding
-// pad, is checked with two Sturm counts and replaces the Gershgorin interval
-// when the counts confirm it (else the Gershgorin interval is kept).
+// minor lies in [brk[k], brk[k + 1]], widened by the rounding pad (checked
+// with two counts).  The bracket does not change the result: the halvings
+// always follow the path of bisection from the Gershgorin interval, and the
+// bracket only lets the halvings whose midpoints fall outside it (by more
+// than the fast count's few-ulp error zone) be taken without a count -- the
+// count there could only have said what the bracket says.  So a minor's
+// eigenvalues have the same bits whether or not its matrix's eigenvalues
+// were ready when it started.
+template <int NT, int S>
+__device__ void bisect_block(int base, int ie, int m, const double *de, double *out, int tid, double gl,
+                             double gu, double pad, double pivmin, double atol, const double *brk) {
+    constexpr double eps = 2.220446049250313e-16;
+    double lo[S], hi[S];
+    int idx[S];
+    bool done[S];
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+        idx[t] = base + t * NT + tid;
+        lo[t] = gl; hi[t] = gu;
+        done[t] = idx[t] >= ie;
+    }
+    // Sturm counts at S points; EXACT: correctly rounded division
+    auto counts = [&](const double (&x)[S], int (&cnt)[S], auto exact) {
+        double q[S];
+#pragma unroll
+        for (int t = 0; t < S; ++t) { q[t] = 1.0; cnt[t] = 0; }
+        for (int i = 0; i < m; ++i) {
+            const double d = de[2 * i], e2 = de[2 * i + 1];
+#pragma unroll
+            for (int t = 0; t < S; ++t) {
+                double v;
+                if constexpr (decltype(exact)::value) {
+                    v = (d - x[t]) - e2 / q[t];
+                } else {
+                    double r = __builtin_amdgcn_rcp(q[t]);
+                    r = fma(fma(-q[t], r, 1.0), r, r);
+                    v = (d - x[t]) - e2 * r;
+                }
+                v = (fabs(v) < pivmin) ? -pivmin : v;   // |q| >= pivmin keeps e2 / q finite
+                cnt[t] += (v < 0.0) ? 1 : 0;
+                q[t] = v;
+            }
+        }
+    };
+    const std::integral_constant<bool, false> fast{};
+    const std::integral_constant<bool, true> exact{};
+    auto stop = [&](int t) {
+        const double w = hi[t] - lo[t];
+        const double mid = 0.5 * (lo[t] + hi[t]);
+        return w <= fmax(2.0 * eps * fmax(fabs(lo[t]), fabs(hi[t])), atol) || mid <= lo[t] || mid >= hi[t];
+    };
+    auto halve = [&](auto form) {
+        for (int it = 0; it < 80; ++it) {
+            bool all = true;
+#pragma unroll
+            for (int t = 0; t < S; ++t) all = all && done[t];
+            if (all) break;
+            double x[S];
+            int cnt[S];
+#pragma unroll
+            for (int t = 0; t < S; ++t) x[t] = 0.5 * (lo[t] + hi[t]);
+            counts(x, cnt, form);
+#pragma unroll
+            for (int t = 0; t < S; ++t) {
+                if (done[t]) continue;
+                if (cnt[t] > idx[t]) hi[t] = x[t]; else lo[t] = x[t];
+                if (stop(t)) done[t] = true;
+            }
+        }
+    };
+    if (brk) {
+        // the bracket, widened by the rounding pad and the fast count's error zone
+        double bl[S], bh[S];
+        int cl[S], ch[S];
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            const int k = done[t] ? 0 : idx[t];
+            bl[t] = fmax(gl, brk[k] - pad);
+            bh[t] = fmin(gu, brk[k + 1] + pad);
+        }
+        counts(bl, cl, fast);
+        counts(bh, ch, fast);
+        const double zone = 64.0 * eps * fmax(fabs(gl), fabs(gu)) + atol;
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            if (done[t] || !(bl[t] < bh[t] && cl[t] <= idx[t] && ch[t] > idx[t])) continue;
+            // take the Gershgorin path's halvings whose midpoints lie outside the bracket
+            for (int it = 0; it < 80 && !stop(t); ++it) {
+                const double x = 0.5 * (lo[t] + hi[t]);
+                if (x < bl[t] - zone) lo[t] = x;
+                else if (x > bh[t] + zone) hi[t] = x;
+                else break;
+            }
+            if (stop(t)) done[t] = true;
+        }
+    }
+    halve(fast);
+    // Certify with the monotone count: a bracket of four stopping widths on
+    // either side of the fast result (its endpoints then lie outside the
+    // few ulp where the fast count can err), widened 64 times or reset to
+    // the Gershgorin interval where that fails; then correctly rounded
+    // halvings (three, typically) back to the stopping width.
+    {
+        int cl[S], ch[S];
+        double mid[S], sw[S];
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            mid[t] = 0.5 * (lo[t] + hi[t]);
+            sw[t] = fmax(2.0 * eps * fmax(fabs(lo[t]), fabs(hi[t])), atol);
+            lo[t] = fmax(gl, mid[t] - 4.0 * sw[t]);
+            hi[t] = fmin(gu, mid[t] + 4.0 * sw[t]);
+        }
+        counts(lo, cl, exact);
+        counts(hi, ch, exact);
+        bool bad = false;
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            done[t] = idx[t] >= ie;
+            bad = bad || (!done[t] && !(cl[t] <= idx[t] && ch[t] > idx[t]));
+        }
+        if (__any(bad)) {
+            bool ok[S];
+#pragma unroll
+            for (int t = 0; t < S; ++t) ok[t] = done[t] || (cl[t] <= idx[t] && ch[t] > idx[t]);
+            double wl[S], wh[S];
+#pragma unroll
+            for (int t = 0; t < S; ++t) {
+                wl[t] = fmax(gl, mid[t] - 256.0 * sw[t]);
+                wh[t] = fmin(gu, mid[t] + 256.0 * sw[t]);
+            }
+            counts(wl, cl, exact);
+            counts(wh, ch, exact);
+#pragma unroll
+            for (int t = 0; t < S; ++t) {
+                if (ok[t]) continue;
+                const bool wok = cl[t] <= idx[t] && ch[t] > idx[t];
+                lo[t] = wok ? wl[t] : gl;
+                hi[t] = wok ? wh[t] : gu;
+            }
+        }
+        halve(exact);
+    }
+#pragma unroll
+    for (int t = 0; t < S; ++t)
+        if (idx[t] < ie) out[idx[t]] = 0.5 * (lo[t] + hi[t]);
+}
+
 template <int NT, int ILP>
 __device__ void bisect_tridiagonal(const double *dg, const double *eg, int m, double *out, double *de,
                                    double *red, int tid, int lane, int wave, const double *brk = nullptr,
@@ -312,126 +459,12 @@ __device__ void bisect_tridiagonal(const double *dg, const double *eg, int m, do
     gl -= pad; gu += pad;
     const double atol = eps * tnorm;
     for (int base = i_begin; base < ie; base += NT * ILP) {
-        double lo[ILP], hi[ILP];
-        int idx[ILP];
-        bool done[ILP];
-#pragma unroll
-        for (int t = 0; t < ILP; ++t) {
-            idx[t] = base + t * NT + tid;
-            lo[t] = gl; hi[t] = gu;
-            done[t] = idx[t] >= ie;
-        }
-        // Sturm counts at ILP points; EXACT: correctly rounded division
-        auto counts = [&](const double (&x)[ILP], int (&cnt)[ILP], auto exact) {
-            double q[ILP];
-#pragma unroll
-            for (int t = 0; t < ILP; ++t) { q[t] = 1.0; cnt[t] = 0; }
-            for (int i = 0; i < m; ++i) {
-                const double d = de[2 * i], e2 = de[2 * i + 1];
-#pragma unroll
-                for (int t = 0; t < ILP; ++t) {
-                    double v;
-                    if constexpr (decltype(exact)::value) {
-                        v = (d - x[t]) - e2 / q[t];
-                    } else {
-                        double r = __builtin_amdgcn_rcp(q[t]);
-                        r = fma(fma(-q[t], r, 1.0), r, r);
-                        v = (d - x[t]) - e2 * r;
-                    }
-                    v = (fabs(v) < pivmin) ? -pivmin : v;   // |q| >= pivmin keeps e2 / q finite
-                    cnt[t] += (v < 0.0) ? 1 : 0;
-                    q[t] = v;
-                }
-            }
-        };
-        const std::integral_constant<bool, false> fast{};
-        const std::integral_constant<bool, true> exact{};
-        auto halve = [&](auto form) {
-            for (int it = 0; it < 80; ++it) {
-                bool all = true;
-#pragma unroll
-                for (int t = 0; t < ILP; ++t) all = all && done[t];
-                if (all) break;
-                double x[ILP];
-                int cnt[ILP];
-#pragma unroll
-                for (int t = 0; t < ILP; ++t) x[t] = 0.5 * (lo[t] + hi[t]);
-                counts(x, cnt, form);
-#pragma unroll
-                for (int t = 0; t < ILP; ++t) {
-                    if (done[t]) continue;
-                    if (cnt[t] > idx[t]) hi[t] = x[t]; else lo[t] = x[t];
-                    const double w = hi[t] - lo[t];
-                    const double mid = 0.5 * (lo[t] + hi[t]);
-                    if (w <= fmax(2.0 * eps * fmax(fabs(lo[t]), fabs(hi[t])), atol) || mid <= lo[t] || mid >= hi[t])
-                        done[t] = true;
-                }
-            }
-        };
-        if (brk) {
-            double bl[ILP], bh[ILP];
-            int cl[ILP], ch[ILP];
-#pragma unroll
-            for (int t = 0; t < ILP; ++t) {
-                const int k = done[t] ? 0 : idx[t];
-                bl[t] = fmax(gl, brk[k] - pad);
-                bh[t] = fmin(gu, brk[k + 1] + pad);
-            }
-            counts(bl, cl, fast);
-            counts(bh, ch, fast);
-#pragma unroll
-            for (int t = 0; t < ILP; ++t)
-                if (!done[t] && bl[t] < bh[t] && cl[t] <= idx[t] && ch[t] > idx[t]) { lo[t] = bl[t]; hi[t] = bh[t]; }
-        }
-        halve(fast);
-        // Certify with the monotone count: a bracket of four stopping widths on
-        // either side of the fast result (its endpoints then lie outside the
-        // few ulp where the fast count can err), widened 64 times or reset to
-        // the Gershgorin interval where that fails; then correctly rounded
-        // halvings (three, typically) back to the stopping width.
-        {
-            int cl[ILP], ch[ILP];
-            double mid[ILP], sw[ILP];
-#pragma unroll
-            for (int t = 0; t < ILP; ++t) {
-                mid[t] = 0.5 * (lo[t] + hi[t]);
-                sw[t] = fmax(2.0 * eps * fmax(fabs(lo[t]), fabs(hi[t])), atol);
-                lo[t] = fmax(gl, mid[t] - 4.0 * sw[t]);
-                hi[t] = fmin(gu, mid[t] + 4.0 * sw[t]);
-            }
-            counts(lo, cl, exact);
-            counts(hi, ch, exact);
-            bool bad = false;
-#pragma unroll
-            for (int t = 0; t < ILP; ++t) {
-                done[t] = idx[t] >= ie;
-                bad = bad || (!done[t] && !(cl[t] <= idx[t] && ch[t] > idx[t]));
-            }
-            if (__any(bad)) {
-                bool ok[ILP];
-#pragma unroll
-                for (int t = 0; t < ILP; ++t) ok[t] = done[t] || (cl[t] <= idx[t] && ch[t] > idx[t]);
-                double wl[ILP], wh[ILP];
-#pragma unroll
-                for (int t = 0; t < ILP; ++t) {
-                    wl[t] = fmax(gl, mid[t] - 256.0 * sw[t]);
-                    wh[t] = fmin(gu, mid[t] + 256.0 * sw[t]);
-                }
-                counts(wl, cl, exact);
-                counts(wh, ch, exact);
-#pragma unroll
-                for (int t = 0; t < ILP; ++t) {
-                    if (ok[t]) continue;
-                    const bool wok = cl[t] <= idx[t] && ch[t] > idx[t];
-                    lo[t] = wok ? wl[t] : gl;
-                    hi[t] = wok ? wh[t] : gu;
-                }
-            }
-            halve(exact);
-        }
-#pragma unroll
-        for (int t = 0; t < ILP; ++t)
-            if (idx[t] < ie) out[idx[t]] = 0.5 * (lo[t] + hi[t]);
+        // eigenvalues per lane in this block (uniform): no chains for empty slots
+        const int slots = min(ILP, (ie - base + NT - 1) / NT);
+        if (slots <= 1) bisect_block<NT, 1>(base, ie, m, de, out, tid, gl, gu, pad, pivmin, atol, brk);
+        else if (slots <= 2) bisect_block<NT, (ILP < 2 ? ILP : 2)>(base, ie, m, de, out, tid, gl, gu, pad, pivmin, atol, brk);
+        else if (slots <= 4) bisect_block<NT, (ILP < 4 ? ILP : 4)>(base, ie, m, de, out, tid, gl, gu, pad, pivmin, atol, brk);
+        else bisect_block<NT, ILP>(base, ie, m, de, out, tid, gl, gu, pad, pivmin, atol, brk);
     }
 }
 
@@ -969,41 +1002,21 @@ struct TriArgs {
     // polls after which a wave waiting for another wave of its workgroup gives
     // up (bounded waits: the problem is then flagged, and the kernel still ends)
     unsigned spin_limit;
-    // 1: every matrix's own problem is in this launch, so its minors wait for
-    // its eigenvalues (interlacing brackets independent of timing)
-    int wait_lambda;
 };
 
 // flags bit of a problem whose bounded inter-wave wait gave up (its outputs are invalid)
 constexpr int32_t FLAG_WAIT_TIMEOUT = 4;
 
 // Bracket source for the bisection of item `it`: the eigenvalues of its
-// matrix if it is a plain minor (published by the workgroup that computed
-// them), else nullptr.  When the launch holds every matrix's own problem
-// (a.wait_lambda), a minor waits for them -- bounded by a.spin_limit polls,
-// after which it flags FLAG_WAIT_TIMEOUT and bisects from the Gershgorin
-// interval -- so that the starting bracket, and with it every bit of the
-// result, does not depend on timing.  The wait always ends: the matrix's own
-// problem has the larger order, so the queue (largest first) hands it out
-// before any of its minors, and it waits for nothing.  Uniform over the
+// matrix if it is a plain minor and they are final already (published by the
+// workgroup that computed them), else nullptr.  The bracket only saves
+// halvings; the result is the same either way (bisect_block), so whether the
+// eigenvalues were ready in time does not change any bit.  Uniform over the
 // workgroup; s_flag is LDS scratch.
 __device__ inline const double *interlacing_bracket(const TriArgs &a, const Item &it, unsigned long long *s_flag) {
     if (it.j < 0 || it.k >= 0) return nullptr;
-    if (threadIdx.x == 0) {
-        unsigned long long p = __hip_atomic_load(&a.lam_ready[it.b], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        if (a.wait_lambda) {
-            unsigned polls = 0;
-            while (p == 0) {
-                if (++polls > a.spin_limit) {
-                    atomicOr(&a.flags[it.b], FLAG_WAIT_TIMEOUT);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(8);
-                p = __hip_atomic_load(&a.lam_ready[it.b], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-            }
-        }
-        *s_flag = p;
-    }
+    if (threadIdx.x == 0)
+        *s_flag = __hip_atomic_load(&a.lam_ready[it.b], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     const unsigned long long p = *s_flag;
     __syncthreads();
