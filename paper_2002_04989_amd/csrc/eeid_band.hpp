@@ -1166,12 +1166,25 @@ struct Band {
         double *yw = u + SMALL_MAX;
         double *ds = yw + SMALL_MAX, *es = ds + SMALL_MAX;
         const int n = it.n, j = it.j;
-        // thread per row r, its entries (r, 0..r)
-        for (int r = tid; r < m; r += NT) {
-            const int rs = r + ((j >= 0 && r >= j) ? 1 : 0);
-            for (int c = 0; c <= r; ++c) {
-                const int cs = c + ((j >= 0 && c >= j) ? 1 : 0);
-                L[pk(r, c)] = (it.k >= 0) ? rotated_at(it.src, n, j, it.k, rs, cs) : lower_at(it.src, n, rs, cs);
+        // all threads over the m x m index space, eight loads in flight per thread
+        // before their stores (the loads are independent; issued one by one they
+        // would serialise on the memory latency)
+        for (int q0 = 0; q0 < m * m; q0 += 8 * NT) {
+            double v[8];
+#pragma unroll
+            for (int z = 0; z < 8; ++z) {
+                const int q = q0 + z * NT + tid, r = q / m, c = q - r * m;
+                v[z] = 0.0;
+                if (q < m * m && c <= r) {
+                    const int rs = r + ((j >= 0 && r >= j) ? 1 : 0);
+                    const int cs = c + ((j >= 0 && c >= j) ? 1 : 0);
+                    v[z] = (it.k >= 0) ? rotated_at(it.src, n, j, it.k, rs, cs) : lower_at(it.src, n, rs, cs);
+                }
+            }
+#pragma unroll
+            for (int z = 0; z < 8; ++z) {
+                const int q = q0 + z * NT + tid, r = q / m, c = q - r * m;
+                if (q < m * m && c <= r) L[pk(r, c)] = v[z];
             }
         }
         __syncthreads();
@@ -1198,13 +1211,27 @@ struct Band {
             if (tau == 0.0) { __syncthreads(); continue; }
             for (int i = t0 + tid; i < m; i += NT) u[i] = (i == t0) ? 1.0 : L[pk(i, k)] * scal;
             __syncthreads();
-            // y = A22 u (thread per row) and the per-wave parts of u^T y
+            // y = A22 u with tpr threads per row (adjacent lanes, each a residue class of
+            // columns, summed across the group): row i's entries (i, t0..i) step
+            // through the packed columns, its entries (i+1.., i) are contiguous in
+            // column i; and the per-wave parts of u^T y
+            const int tpr = (m <= NT / 4) ? 4 : ((m <= NT / 2) ? 2 : 1);
             double part = 0.0;
-            for (int i = t0 + tid; i < m; i += NT) {
-                double y = 0.0;
-                for (int c = t0; c < m; ++c) y = fma((c <= i) ? L[pk(i, c)] : L[pk(c, i)], u[c], y);
-                yw[i] = y;
-                part = fma(u[i], y, part);
+            for (int i0 = t0; i0 < m; i0 += NT / tpr) {
+                const int i = i0 + tid / tpr, sub = tid % tpr;
+                double y0 = 0.0, y1 = 0.0;
+                if (i < m) {
+                    for (int c = t0 + sub; c <= i; c += tpr) y0 = fma(L[pk(i, c)], u[c], y0);
+                    const int qd = pk(i, i) - i;
+                    for (int c = i + 1 + sub; c < m; c += tpr) y1 = fma(L[qd + c], u[c], y1);
+                }
+                double y = y0 + y1;
+                if (tpr >= 2) y = psum<1>(y);
+                if (tpr >= 4) y = psum<2>(y);
+                if (i < m && sub == 0) {
+                    yw[i] = y;
+                    part = fma(u[i], y, part);
+                }
             }
             part = wave_sum(part);
             if (lane == 0) red[8 + wave] = part;
@@ -1214,10 +1241,12 @@ struct Band {
             const double kap = 0.5 * tau * tau * uy;
             for (int i = t0 + tid; i < m; i += NT) yw[i] = fma(-kap, u[i], tau * yw[i]);   // y -> w
             __syncthreads();
-            // A22 -= u w^T + w u^T on the packed trailing triangle, thread per row
-            for (int r = t0 + tid; r < m; r += NT) {
+            // A22 -= u w^T + w u^T on the packed trailing triangle, tpr threads per row
+            for (int r0 = t0; r0 < m; r0 += NT / tpr) {
+                const int r = r0 + tid / tpr, sub = tid % tpr;
+                if (r >= m) continue;
                 const double ur = u[r], wr = yw[r];
-                for (int c = t0; c <= r; ++c) L[pk(r, c)] -= fma(ur, yw[c], wr * u[c]);
+                for (int c = t0 + sub; c <= r; c += tpr) L[pk(r, c)] -= fma(ur, yw[c], wr * u[c]);
             }
             __syncthreads();
         }
