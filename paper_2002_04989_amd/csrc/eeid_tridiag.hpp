@@ -275,7 +275,8 @@ struct Panel {
 // therefore comes from a bracket certified by the monotone count.
 //
 // i_begin, i_end: only eigenvalues i_begin .. i_end - 1 are computed (the
-// workgroup's share when several share one tridiagonal); default all.
+// workgroup's share when several share one tridiagonal); default all.  Small
+// tridiagonals (all eigenvalues, m <= NT / 2) use multisect_small instead.
 //
 // brk (optional): the m + 1 ascending eigenvalues of a matrix of which T is
 // similar to a principal minor.  By Cauchy interlacing eigenvalue k of the
@@ -426,6 +427,100 @@ __device__ void bisect_block(int base, int ie, int m, const double *de, double *
         if (idx[t] < ie) out[idx[t]] = 0.5 * (lo[t] + hi[t]);
 }
 
+// Small tridiagonals (m <= NT / 2): multisection.  Eigenvalue k gets a group
+// of L adjacent lanes (L = 2, 4, 8 or 16, as many as fit), which count at L
+// points dividing [lo, hi] into L + 1 equal parts; the first point whose count
+// exceeds k and the one before it bound the new interval, so each round gains
+// log2(L + 1) bits instead of one (the bisection of one eigenvalue per lane
+// leaves most lanes idle for small m).  Same counts, certification and
+// bracket use as bisect_block: the rounds follow the path from the Gershgorin
+// interval, and a round whose points all lie outside the interlacing bracket
+// (beyond the fast count's error zone) is decided without counts.
+template <int NT>
+__device__ void multisect_small(int m, const double *de, double *out, int tid, int lane, double gl, double gu,
+                                double pad, double pivmin, double atol, const double *brk) {
+    constexpr double eps = 2.220446049250313e-16;
+    const int L = (NT / m >= 16) ? 16 : ((NT / m >= 8) ? 8 : ((NT / m >= 4) ? 4 : 2));
+    const int k = tid / L, p = tid % L;
+    const bool live = k < m;
+    const int kk = live ? k : m - 1;   // idle lanes shadow the last eigenvalue; their results are not stored
+    const int gbase = lane & ~(L - 1);
+    const unsigned long long gmask = (1ull << L) - 1;
+    double lo = gl, hi = gu;
+    auto count1 = [&](double x, auto exact) {
+        double q = 1.0;
+        int cnt = 0;
+        for (int i = 0; i < m; ++i) {
+            const double d = de[2 * i], e2 = de[2 * i + 1];
+            double v;
+            if constexpr (decltype(exact)::value) {
+                v = (d - x) - e2 / q;
+            } else {
+                double r = __builtin_amdgcn_rcp(q);
+                r = fma(fma(-q, r, 1.0), r, r);
+                v = (d - x) - e2 * r;
+            }
+            v = (fabs(v) < pivmin) ? -pivmin : v;
+            cnt += (v < 0.0) ? 1 : 0;
+            q = v;
+        }
+        return cnt;
+    };
+    const std::integral_constant<bool, false> fast{};
+    const std::integral_constant<bool, true> exact{};
+    auto point = [&](int qq) { return lo + (hi - lo) * ((double)(qq + 1) / (double)(L + 1)); };
+    auto finished = [&]() {
+        const double mid = 0.5 * (lo + hi);
+        return (hi - lo) <= fmax(2.0 * eps * fmax(fabs(lo), fabs(hi)), atol) || mid <= lo || mid >= hi;
+    };
+    double bl = -1e308, bh = 1e308;
+    bool fwd = false;
+    if (brk) {
+        bl = fmax(gl, brk[kk] - pad);
+        bh = fmin(gu, brk[kk + 1] + pad);
+        const int cl = count1(bl, fast), ch = count1(bh, fast);
+        fwd = bl < bh && cl <= kk && ch > kk;   // the same in every lane of the group
+    }
+    const double zone = 64.0 * eps * fmax(fabs(gl), fabs(gu)) + atol;
+    auto rounds = [&](auto form, bool use_fwd) {
+        for (int it = 0; it < 80; ++it) {
+            const bool fin = finished();
+            if (__all(fin)) break;
+            const double x = point(p);
+            const bool inside = x >= bl - zone && x <= bh + zone;
+            const bool known = use_fwd && !((__ballot(inside) >> gbase) & gmask);   // no point of the group inside
+            int c = 0;
+            if (__any(!known)) c = count1(x, form);
+            const bool above = known ? (x > bh + zone) : (c > kk);
+            const unsigned long long bits = (__ballot(above) >> gbase) & gmask;
+            const int first = bits ? __ffsll((long long)bits) - 1 : L;
+            const double nlo = (first == 0) ? lo : point(first - 1);
+            const double nhi = (first == L) ? hi : point(first);
+            if (!fin) { lo = nlo; hi = nhi; }
+        }
+    };
+    rounds(fast, fwd);
+    // certify: a bracket of four stopping widths on either side (every lane of
+    // the group counts both ends), else 64 times wider, else Gershgorin; then
+    // rounds with correctly rounded counts back to the stopping width
+    const double mid = 0.5 * (lo + hi);
+    const double sw = fmax(2.0 * eps * fmax(fabs(lo), fabs(hi)), atol);
+    double clo = fmax(gl, mid - 4.0 * sw), chi = fmin(gu, mid + 4.0 * sw);
+    bool ok = count1(clo, exact) <= kk && count1(chi, exact) > kk;
+    if (__any(!ok)) {
+        const double wl = fmax(gl, mid - 256.0 * sw), wh = fmin(gu, mid + 256.0 * sw);
+        const bool wok = count1(wl, exact) <= kk && count1(wh, exact) > kk;
+        if (!ok) {
+            clo = wok ? wl : gl;
+            chi = wok ? wh : gu;
+        }
+    }
+    lo = clo;
+    hi = chi;
+    rounds(exact, false);
+    if (live && p == 0) out[k] = 0.5 * (lo + hi);
+}
+
 template <int NT, int ILP>
 __device__ void bisect_tridiagonal(const double *dg, const double *eg, int m, double *out, double *de,
                                    double *red, int tid, int lane, int wave, const double *brk = nullptr,
@@ -458,6 +553,10 @@ __device__ void bisect_tridiagonal(const double *dg, const double *eg, int m, do
     const double pad = 2.0 * eps * tnorm * (double)m + 4.0 * pivmin;
     gl -= pad; gu += pad;
     const double atol = eps * tnorm;
+    if (i_begin == 0 && ie == m && 2 * m <= NT) {
+        multisect_small<NT>(m, de, out, tid, lane, gl, gu, pad, pivmin, atol, brk);
+        return;
+    }
     for (int base = i_begin; base < ie; base += NT * ILP) {
         // eigenvalues per lane in this block (uniform): no chains for empty slots
         const int slots = min(ILP, (ie - base + NT - 1) / NT);
