@@ -53,7 +53,8 @@ struct Band {
     static constexpr int RED = 2 * BW + 8;
 
     S *tiles;
-    double *V, *Wm, *bnd, *dg, *eg;    // slot
+    double *V, *Wm, *bnd, *dg, *eg;    // slot; V, Wm: the current panel's columns of V0, W0
+    double *V0, *W0;                   // slot: V and W of a pair of panels (2 BW columns each)
     double *Tm, *Mm, *Nm;              // LDS: T, V^T X, T^T V^T X (BW x BW each); SYR2K staging from Tm on
     double *red, *vec;                 // LDS: per-wave partial sums, small vectors
     double *de;                        // LDS: bisection (aliases the stage-1 and chase region)
@@ -518,16 +519,13 @@ struct Band {
         }
     }
 
-    __device__ void make_w(int J1, int r0) {
-        // X = Y T (T upper triangular, its lower part zero in LDS); each block's Y
-        // is read before its X is written, by the same wave
-        rows_times_small<false>(r0, Wm, Tm, 0.0);
-        __syncthreads();
-        // per-wave partial sums of M, added in wave order afterwards (a fixed
-        // order: reruns give the same bits)
+    // dst = P^T Q (BW x BW, dst(i, j) at [i * BW + j]) over rows [r0, LD) of
+    // P and Q (column l at l * LD): rows in chunks of 4 per MFMA, chunks dealt
+    // to waves, per-wave partial sums added in wave order afterwards (a fixed
+    // order: reruns give the same bits).  dst must not overlap Nm + BW^2 on.
+    __device__ void cross_sum(const double *P, const double *Q, int r0, double *dst) {
         double *part = Nm + BW * BW;
         {
-            // M(i, j) = sum_r V(r, i) X(r, j): rows in chunks of 4 per MFMA, chunks dealt to waves
             const int lr = lane & 15, lk = lane >> 4;
             dbl4 acc[2][2];
 #pragma unroll
@@ -536,8 +534,8 @@ struct Band {
                 double av[2], bx[2];
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
-                    av[q] = V[(int64_t)(q * 16 + lr) * LD + rk + lk];
-                    bx[q] = Wm[(int64_t)(q * 16 + lr) * LD + rk + lk];
+                    av[q] = P[(int64_t)(q * 16 + lr) * LD + rk + lk];
+                    bx[q] = Q[(int64_t)(q * 16 + lr) * LD + rk + lk];
                 }
 #pragma unroll
                 for (int ib = 0; ib < 2; ++ib)
@@ -557,9 +555,17 @@ struct Band {
         for (int q = tid; q < BW * BW; q += NT) {
             double sum = part[q];
             for (int w = 1; w < NWAVE; ++w) sum += part[w * BW * BW + q];
-            Mm[q] = sum;
+            dst[q] = sum;
         }
         __syncthreads();
+    }
+
+    __device__ void make_w(int J1, int r0) {
+        // X = Y T (T upper triangular, its lower part zero in LDS); each block's Y
+        // is read before its X is written, by the same wave
+        rows_times_small<false>(r0, Wm, Tm, 0.0);
+        __syncthreads();
+        cross_sum(V, Wm, r0, Mm);   // M = V^T X
         for (int q = tid; q < BW * BW; q += NT) {
             const int i = q / BW, j = q % BW;
             double s = 0.0;
@@ -576,14 +582,17 @@ struct Band {
     }
 
     // ---------------------------------------------------------------- SYR2K
-    // C(I, J) -= V_I W_J^T + W_I V_J^T for tiles J >= J1, a group of tile
-    // columns at a time (two in FP64, four in FP32): their J-side rows are
-    // staged in LDS (tile column J + j at stg + j * 2 BW TILE, V then W, column
-    // k of the panel at [k * TILE + row]), and the I-side rows of each row
+    // C(I, J) -= V_I W_J^T + W_I V_J^T for tiles J in [J1, J2), I >= J, with
+    // the first KW columns of V and W (KW = BW: one panel; 2 BW: a pair of
+    // panels, V = [V_p V_p+1], W = [W_p W_p+1]), a group of tile columns at a
+    // time (FP64: two for one panel, one for a pair; FP32: four, two): their
+    // J-side rows are staged in LDS (tile column J + j at stg + j * 2 KW TILE,
+    // V then W, column k at [k * TILE + row]), and the I-side rows of each row
     // block are loaded once for the NJ tiles of the row in the group.
     // 16-row blocks (FP64 trailing matrix)
-    template <int NJ>
-    __device__ void syr2k_rows16(int I, int J, const double *stg, int ib0, int ibstep) {
+    template <int NJ, int KW>
+    __device__ void syr2k_rows16(int I, int J, const double *stg, const double *vb, const double *wb, int ib0,
+                                 int ibstep) {
         typedef typename std::conditional<sizeof(S) == 8, double, float>::type OpT;
         typedef typename std::conditional<sizeof(S) == 8, dbl4, flt4>::type AccT;
 #pragma unroll 1
@@ -593,11 +602,11 @@ struct Band {
             int ln = lane;
             asm volatile("" : "+v"(ln));
             const int lr = ln & 15, lk = ln >> 4;
-            const double *vI = V + I * TILE + lr, *wI = Wm + I * TILE + lr;
+            const double *vI = vb + I * TILE + lr, *wI = wb + I * TILE + lr;
             // I-side operands of rows ib * 16 + lr, all K
-            OpT bv[BW / 4], bw[BW / 4];
+            OpT bv[KW / 4], bw[KW / 4];
 #pragma unroll
-            for (int kk = 0; kk < BW / 4; ++kk) {
+            for (int kk = 0; kk < KW / 4; ++kk) {
                 const int64_t col = (int64_t)(4 * kk + lk) * LD + ib * 16;
                 bv[kk] = (OpT)vI[col];
                 bw[kk] = (OpT)wI[col];
@@ -605,12 +614,12 @@ struct Band {
 #pragma unroll
             for (int j = 0; j < NJ; ++j) {
                 S *tp = tile_ptr(I, J + j);
-                const double *vs = stg + j * 2 * BW * TILE, *ws = vs + BW * TILE;
+                const double *vs = stg + j * 2 * KW * TILE, *ws = vs + KW * TILE;
                 AccT acc[4];
 #pragma unroll
                 for (int jb = 0; jb < 4; ++jb) acc[jb] = AccT{0, 0, 0, 0};
 #pragma unroll
-                for (int kk = 0; kk < BW / 4; ++kk) {
+                for (int kk = 0; kk < KW / 4; ++kk) {
                     const int sc = (4 * kk + lk) * TILE + lr;
                     OpT aw[4], av[4];
 #pragma unroll
@@ -650,8 +659,9 @@ struct Band {
 
     // 32-row blocks (FP32 trailing matrix: its operands take half the registers);
     // stg holds FP32 copies of the J-side rows of up to four tile columns
-    template <int NJ>
-    __device__ void syr2k_rows32(int I, int J, const float *stg, int ip0, int ipstep) {
+    template <int NJ, int KW>
+    __device__ void syr2k_rows32(int I, int J, const float *stg, const double *vb, const double *wb, int ip0,
+                                 int ipstep) {
         typedef typename std::conditional<sizeof(S) == 8, double, float>::type OpT;
         typedef typename std::conditional<sizeof(S) == 8, dbl4, flt4>::type AccT;
 #pragma unroll 1
@@ -661,11 +671,11 @@ struct Band {
             int ln = lane;
             asm volatile("" : "+v"(ln));
             const int lr = ln & 15, lk = ln >> 4;
-            const double *vI = V + I * TILE + lr, *wI = Wm + I * TILE + lr;
+            const double *vI = vb + I * TILE + lr, *wI = wb + I * TILE + lr;
             // I-side operands of rows (ip + q) * 16 + lr, all K
-            OpT bv[BW / 4][2], bw[BW / 4][2];
+            OpT bv[KW / 4][2], bw[KW / 4][2];
 #pragma unroll
-            for (int kk = 0; kk < BW / 4; ++kk) {
+            for (int kk = 0; kk < KW / 4; ++kk) {
                 const int64_t col = (int64_t)(4 * kk + lk) * LD + ip * 16;
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
@@ -676,12 +686,12 @@ struct Band {
 #pragma unroll
             for (int j = 0; j < NJ; ++j) {
                 S *tp = tile_ptr(I, J + j);
-                const float *vs = stg + j * 2 * BW * TILE, *ws = vs + BW * TILE;
+                const float *vs = stg + j * 2 * KW * TILE, *ws = vs + KW * TILE;
                 AccT acc[4][2];
 #pragma unroll
                 for (int jb = 0; jb < 4; ++jb) { acc[jb][0] = AccT{0, 0, 0, 0}; acc[jb][1] = AccT{0, 0, 0, 0}; }
 #pragma unroll
-                for (int kk = 0; kk < BW / 4; ++kk) {
+                for (int kk = 0; kk < KW / 4; ++kk) {
                     const int sc = (4 * kk + lk) * TILE + lr;
                     OpT aw[4], av[4];
 #pragma unroll
@@ -734,44 +744,55 @@ struct Band {
     static constexpr int B0STEP = (NWAVE >= BPR) ? BPR : 1;
     __device__ int block0() const { return (NWAVE >= BPR) ? wave % BPR : 0; }
 
-    __device__ void syr2k(int J1) {
+    template <int KW>
+    __device__ void syr2k(int J1, int J2, const double *vb, const double *wb) {
         if constexpr (sizeof(S) == 8) {
+            constexpr int G = 2 * BW / KW;   // tile columns per group (the staging holds 4 BW TILE doubles)
             double *stg = Tm;   // T, M and N are not needed again in this panel
-            for (int J = J1; J < T; J += 2) {
-                const int nj = min(2, T - J);
-                for (int q = tid; q < nj * BW * TILE; q += NT) {
-                    const int j = q / (BW * TILE), qq = q % (BW * TILE);
+            for (int J = J1; J < J2; J += G) {
+                const int nj = min(G, J2 - J);
+                for (int q = tid; q < nj * KW * TILE; q += NT) {
+                    const int j = q / (KW * TILE), qq = q % (KW * TILE);
                     const int kc = qq / TILE, r = qq % TILE;
-                    stg[j * 2 * BW * TILE + qq] = V[(int64_t)kc * LD + (J + j) * TILE + r];
-                    stg[j * 2 * BW * TILE + BW * TILE + qq] = Wm[(int64_t)kc * LD + (J + j) * TILE + r];
+                    stg[j * 2 * KW * TILE + qq] = vb[(int64_t)kc * LD + (J + j) * TILE + r];
+                    stg[j * 2 * KW * TILE + KW * TILE + qq] = wb[(int64_t)kc * LD + (J + j) * TILE + r];
                 }
                 __syncthreads();
-                // row J holds one tile of the pair (the other is above the diagonal)
+                // row J holds one tile of the group (the other is above the diagonal)
                 for (int I = J + wave / BPR; I < T; I += RSTEP) {
-                    if (I == J || nj == 1) syr2k_rows16<1>(I, J, stg, block0(), B0STEP);
-                    else syr2k_rows16<2>(I, J, stg, block0(), B0STEP);
+                    if constexpr (G == 1) {
+                        syr2k_rows16<1, KW>(I, J, stg, vb, wb, block0(), B0STEP);
+                    } else {
+                        if (I == J || nj == 1) syr2k_rows16<1, KW>(I, J, stg, vb, wb, block0(), B0STEP);
+                        else syr2k_rows16<2, KW>(I, J, stg, vb, wb, block0(), B0STEP);
+                    }
                 }
                 __syncthreads();
             }
         } else {
-            // FP32 operands (the update's arithmetic is FP32): four tile columns fit
+            // FP32 operands (the update's arithmetic is FP32)
+            constexpr int G = 4 * BW / KW;
             float *stg = reinterpret_cast<float *>(Tm);
-            for (int J = J1; J < T; J += 4) {
-                const int nj = min(4, T - J);
-                for (int q = tid; q < nj * BW * TILE; q += NT) {
-                    const int j = q / (BW * TILE), qq = q % (BW * TILE);
+            for (int J = J1; J < J2; J += G) {
+                const int nj = min(G, J2 - J);
+                for (int q = tid; q < nj * KW * TILE; q += NT) {
+                    const int j = q / (KW * TILE), qq = q % (KW * TILE);
                     const int kc = qq / TILE, r = qq % TILE;
-                    stg[j * 2 * BW * TILE + qq] = (float)V[(int64_t)kc * LD + (J + j) * TILE + r];
-                    stg[j * 2 * BW * TILE + BW * TILE + qq] = (float)Wm[(int64_t)kc * LD + (J + j) * TILE + r];
+                    stg[j * 2 * KW * TILE + qq] = (float)vb[(int64_t)kc * LD + (J + j) * TILE + r];
+                    stg[j * 2 * KW * TILE + KW * TILE + qq] = (float)wb[(int64_t)kc * LD + (J + j) * TILE + r];
                 }
                 __syncthreads();
                 // row J + k holds k + 1 tiles of the group (the rest are above the diagonal)
                 for (int I = J + wave / BPR; I < T; I += RSTEP) {
                     const int ntl = min(nj, I - J + 1);
-                    if (ntl == 1) syr2k_rows32<1>(I, J, stg, 2 * block0(), 2 * B0STEP);
-                    else if (ntl == 2) syr2k_rows32<2>(I, J, stg, 2 * block0(), 2 * B0STEP);
-                    else if (ntl == 3) syr2k_rows32<3>(I, J, stg, 2 * block0(), 2 * B0STEP);
-                    else syr2k_rows32<4>(I, J, stg, 2 * block0(), 2 * B0STEP);
+                    if (ntl == 1) syr2k_rows32<1, KW>(I, J, stg, vb, wb, 2 * block0(), 2 * B0STEP);
+                    else if constexpr (G >= 2) {
+                        if (ntl == 2) syr2k_rows32<2, KW>(I, J, stg, vb, wb, 2 * block0(), 2 * B0STEP);
+                        else if constexpr (G >= 4) {
+                            if (ntl == 3) syr2k_rows32<3, KW>(I, J, stg, vb, wb, 2 * block0(), 2 * B0STEP);
+                            else syr2k_rows32<4, KW>(I, J, stg, vb, wb, 2 * block0(), 2 * B0STEP);
+                        }
+                    }
                 }
                 __syncthreads();
             }
@@ -779,25 +800,43 @@ struct Band {
     }
 
     // --------------------------------------------------------------- stage 1
+    // Diagonal block A(k0:k0+kb, k0:k0+kb) is final: lower triangle to the
+    // band.  Then V and W of the panel (the current V, Wm) are cleared from the
+    // first tile row its update can touch, and T.
+    __device__ void begin_panel(int k0) {
+        const int kb = min(BW, m - k0);
+        for (int q = tid; q < BW * BW; q += NT) {
+            const int i = q % BW, j = q / BW;
+            if (j <= i && i < kb) bnd[(int64_t)(k0 + j) * BLD + (i - j)] = Mget(k0 + i, k0 + j);
+        }
+        if (k0 + BW >= m) return;
+        const int rz = (k0 / TILE) * TILE, len = LD - rz;
+        for (int q = tid; q < BW * len; q += NT) {
+            const int l = q / len, r = rz + q % len;
+            V[(int64_t)l * LD + r] = 0.0;
+            Wm[(int64_t)l * LD + r] = 0.0;
+        }
+        for (int q = tid; q < BW * BW; q += NT) Tm[q] = 0.0;
+    }
+
+    // Panels go in pairs (p at k0 = 64 q, p + 1 at k0 + BW) with one update of
+    // the trailing matrix for both: after panel p only tile column q (which
+    // holds panel p + 1) is updated; panel p + 1 is factored from it, and its
+    // Y = A' V_p+1 with A' = A - V_p W_p^T - W_p V_p^T is formed from the
+    // trailing matrix A not yet updated by panel p:
+    //   Y = A V_p+1 - V_p (W_p^T V_p+1) - W_p (V_p^T V_p+1);
+    // then A <- A - V W^T - W V^T with V = [V_p V_p+1], W = [W_p W_p+1] (rank
+    // 4 BW) over tile columns >= q + 1.  One read-modify-write of the trailing
+    // triangle per pair instead of one per panel.  A last panel without a
+    // partner is updated alone.
     __device__ void reduce_to_band() {
-        for (int k0 = 0; k0 < m; k0 += BW) {
-            const int kb = min(BW, m - k0);
-            // diagonal block A(k0:k0+kb, k0:k0+kb) is final: lower triangle to the band
-            for (int q = tid; q < BW * BW; q += NT) {
-                const int i = q % BW, j = q / BW;
-                if (j <= i && i < kb) bnd[(int64_t)(k0 + j) * BLD + (i - j)] = Mget(k0 + i, k0 + j);
-            }
+        int k0 = 0;
+        while (k0 < m) {
+            V = V0;
+            Wm = W0;
+            begin_panel(k0);
             const int r0 = k0 + BW;
             if (r0 >= m) break;
-            {   // clear V and W from the first tile row the update can touch
-                const int rz = (k0 / TILE) * TILE, len = LD - rz;
-                for (int q = tid; q < BW * len; q += NT) {
-                    const int l = q / len, r = rz + q % len;
-                    V[(int64_t)l * LD + r] = 0.0;
-                    Wm[(int64_t)l * LD + r] = 0.0;
-                }
-                for (int q = tid; q < BW * BW; q += NT) Tm[q] = 0.0;
-            }
             __syncthreads();
             EEID_PHASE_MARK(clk, 4);
             panel_qr(k0);
@@ -809,9 +848,38 @@ struct Band {
             make_w(J1, r0);
             __syncthreads();
             EEID_PHASE_MARK(clk, 3);
-            syr2k(J1);
+            const bool pair = (k0 % TILE == 0) && (r0 + BW < m);
+            syr2k<BW>(J1, pair ? J1 + 1 : T, V0, W0);
             __syncthreads();
             EEID_PHASE_MARK(clk, 4);
+            if (!pair) {
+                k0 += BW;
+                continue;
+            }
+            // ---- panel p + 1: columns r0 .. r0 + BW - 1, trailing rows from r1
+            const int r1 = r0 + BW, J2 = r1 / TILE;
+            V = V0 + (int64_t)BW * LD;
+            Wm = W0 + (int64_t)BW * LD;
+            begin_panel(r0);
+            __syncthreads();
+            EEID_PHASE_MARK(clk, 4);
+            panel_qr(r0);
+            EEID_PHASE_MARK(clk, 1);
+            symm(J2);
+            __syncthreads();
+            EEID_PHASE_MARK(clk, 2);
+            cross_sum(W0, V, r1, Mm);   // W_p^T V_p+1
+            cross_sum(V0, V, r1, Nm);   // V_p^T V_p+1
+            rows_times_small<true>(r1, V0, Mm, 1.0);
+            rows_times_small<true>(r1, W0, Nm, 1.0);
+            __syncthreads();
+            make_w(J2, r1);
+            __syncthreads();
+            EEID_PHASE_MARK(clk, 3);
+            syr2k<2 * BW>(J2, T, V0, W0);
+            __syncthreads();
+            EEID_PHASE_MARK(clk, 4);
+            k0 = r1;
         }
     }
 
@@ -1267,7 +1335,7 @@ template <class S>
 __host__ __device__ inline int64_t slot_bytes_band(int LDmax) {
     const int64_t T = LDmax / TILE;
     const int64_t tiles = T * (T + 1) / 2 * TILE_ELEMS * (int64_t)sizeof(S);
-    const int64_t panel = 2 * (int64_t)BW * LDmax * 8;
+    const int64_t panel = 4 * (int64_t)BW * LDmax * 8;   // V and W of a pair of panels
     const int64_t band = (int64_t)(LDmax + BW) * BLD * 8;
     const int64_t de = 2 * (int64_t)LDmax * 8;
     return ((tiles + 255) / 256) * 256 + panel + band + de;
@@ -1334,9 +1402,11 @@ void band_bisect_kernel(TriArgs args) {
         t.tiles = reinterpret_cast<S *>(slot);
         const int64_t T = t.T;
         const int64_t tile_bytes = ((T * (T + 1) / 2 * TILE_ELEMS * (int64_t)sizeof(S) + 255) / 256) * 256;
-        t.V = reinterpret_cast<double *>(slot + tile_bytes);
-        t.Wm = t.V + (int64_t)BW * t.LD;
-        t.bnd = t.Wm + (int64_t)BW * t.LD;
+        t.V0 = reinterpret_cast<double *>(slot + tile_bytes);
+        t.W0 = t.V0 + (int64_t)2 * BW * t.LD;
+        t.V = t.V0;
+        t.Wm = t.W0;
+        t.bnd = t.W0 + (int64_t)2 * BW * t.LD;
         t.dg = t.bnd + (int64_t)BLD * (t.LD + BW);
         t.eg = t.dg + t.LD;
         if (it.m <= Band<S, NT>::SMALL_MAX) {
