@@ -302,7 +302,6 @@ def cpu_baseline(mats, rounds=128, max_threads=16):
 def host_library(mats, budget_s=8.0):
     """Context, not the oracle: numpy/LAPACK eigvalsh for the EigenValues step on this host."""
     import numpy as np
-    import oracle
     try:
         from threadpoolctl import threadpool_info
         blas_threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
@@ -311,12 +310,13 @@ def host_library(mats, budget_s=8.0):
     A = mats[0]
     n = A.shape[0]
     t0 = time.perf_counter()
-    oracle.eigvalsh(A, "lapack")
+    np.linalg.eigvalsh(A, UPLO="L")
     t_lam = time.perf_counter() - t0
     rng = np.random.default_rng(2)
     k, t_min = 0, 0.0
     while t_min < budget_s and k < n:
-        M = oracle.minor(A, int(rng.integers(0, n)))
+        j = int(rng.integers(0, n))
+        M = np.delete(np.delete(A, j, axis=0), j, axis=1)
         t1 = time.perf_counter()
         np.linalg.eigvalsh(M, UPLO="L")
         t_min += time.perf_counter() - t1
@@ -326,6 +326,73 @@ def host_library(mats, budget_s=8.0):
             "kind": "host library (numpy/LAPACK eigvalsh), not the oracle", "cpu": cpu_model(),
             "sample": f"lambda(A) + {k} random minors of the GOE n={n} matrix, extrapolated to 2 x ({n}+1) "
                       f"problems (EigenValues step only)"}
+
+
+def golden_errors(name, lam, mu, W, member=None):
+    """Errors of one matrix's results against the stored oracle values of `name`."""
+    import numpy as np
+    g = load_golden(name)
+    if g is None:
+        return None
+    sfx = "" if member is None else f"_{member}"
+    js = g["js" + sfx]
+    s = float(np.max(np.abs(g["lam" + sfx])))
+    return {"oracle_minors": len(js), "max_abs_dlam_rel": float(np.max(np.abs(lam - g["lam" + sfx])) / s),
+            "max_abs_dmu_rel": float(np.max(np.abs(mu[js] - g["mu" + sfx])) / s),
+            "max_abs_dW": float(np.max(np.abs(W[:, js] - g["W" + sfx]))),
+            "row_sum_residual": float(np.max(np.abs(W.sum(axis=1) - 1.0))),
+            "col_sum_residual": float(np.max(np.abs(W.sum(axis=0) - 1.0)))}
+
+
+def other_workloads(steps=(20, 3, 2)):
+    """The three smaller workloads, each as one call over its whole batch
+    (eigenvalues of every matrix and minor, then Eq. (2)), inputs resident in
+    HBM: GOE n=64 (median of 20 steps), GOE n=512 (3 steps) and the uneven
+    batch of 256 (2 steps of a hipGraph-captured launch, kernel configuration
+    autotuned), with errors against the stored oracle values."""
+    import numpy as np
+    import torch
+    from paper_2002_04989_amd import eeid, inputs
+    out = {}
+    for (name, k, nsteps) in (("goe64", 1, steps[0]), ("goe512", 2, steps[1]), ("uneven256", 3, steps[2])):
+        mats = inputs.make_config(k)
+        n = [m.shape[0] for m in mats]
+        dev = [torch.from_numpy(m).to("cuda:0") for m in mats]
+        torch.cuda.synchronize()
+        graph = name == "uneven256"
+        if graph:
+            eeid.set_graph_mode(True)
+        try:
+            res, wall, tri, idn, tuned, spread = run_form(dev, n, "fp64", nsteps, 1, tune=graph)
+        finally:
+            if graph:
+                eeid.set_graph_mode(False)
+                eeid.set_variant(None)
+        lam = eeid.split(res[0].cpu().numpy(), n, "lambda")
+        mu = eeid.split(res[1].cpu().numpy(), n, "mu")
+        W = eeid.split(res[2].cpu().numpy(), n, "V2")
+        flags = [int(x) for x in res[3].cpu().numpy()]
+        comps = sum(m * m for m in n)
+        row = {"matrices": len(n), "problems": sum(m + 1 for m in n), "components": comps,
+               "ms_per_step": round(spread["median"], 3), "step_ms": spread,
+               "value": comps / (spread["median"] * 1e-3), "unit": "components/s",
+               "eigenvalue_kernel_ms": round(tri, 3), "identity_ms": round(idn, 3),
+               "flags_nonzero": int(sum(1 for f in flags if f))}
+        if graph:
+            row["launch"] = "hipGraph replay"
+            row["variant"] = tuned[0] if tuned else None
+        if name == "uneven256":
+            g = load_golden(name)
+            errs = {}
+            if g is not None:
+                for b in (int(x) for x in g["members"]):
+                    errs[f"member{b}_n{n[b]}"] = golden_errors(name, lam[b], mu[b], W[b], b)
+            row["errors_vs_oracle"] = errs
+        else:
+            row["errors_vs_oracle"] = golden_errors(name, lam[0], mu[0], W[0])
+        log(f"{name}: {row['ms_per_step']} ms per step")
+        out[name] = row
+    return out
 
 
 # Table 1 of the paper (Section 4): one component of one eigenvector on a 4-core
@@ -403,6 +470,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the (untimed) autotuning of kernel configurations")
     ap.add_argument("--no-paired", action="store_true", help="skip timing the paired form of the identity")
     ap.add_argument("--no-latency", action="store_true", help="skip the single-component latency table")
+    ap.add_argument("--no-others", action="store_true", help="skip the smaller workloads (n=64, n=512, uneven batch)")
     ap.add_argument("--variant", default=None, help="use this kernel configuration (eeid.VARIANTS) instead of autotuning")
     ap.add_argument("--copy-ref", action="store_true",
                     help="run a 1 GiB device copy first (reference for HBM counter scaling)")
@@ -486,6 +554,10 @@ def main():
                 "errors_vs_oracle": errors(mats, truth, h32[0], h32[1], h32[2], n),
                 "flags": [int(x) for x in h32[3]]}
 
+    others = None
+    if not args.no_others:
+        log("smaller workloads")
+        others = other_workloads()
     latency = None
     if not args.no_latency:
         log("single-component latency (Table 1 sizes)")
@@ -512,6 +584,7 @@ def main():
         "fp32_form": fp32,
         "identity_paired_form": paired,
         "single_component_latency": latency,
+        "other_workloads": others,
         "kernel_sources_hash": kernel_sources_hash(),
     }
     print(json.dumps(out), flush=True)
