@@ -54,7 +54,7 @@ struct Band {
 
     S *tiles;
     double *V, *Wm, *bnd, *dg, *eg;    // slot; V, Wm: the current panel's columns of V0, W0
-    double *V0, *W0;                   // slot: V and W of a pair of panels (2 BW columns each)
+    double *V0, *W0;                   // slot: V and W of a pair of panels (2 BW columns each; FP32: BW)
     double *Tm, *Mm, *Nm;              // LDS: T, V^T X, T^T V^T X (BW x BW each); SYR2K staging from Tm on
     double *red, *vec;                 // LDS: per-wave partial sums, small vectors
     double *de;                        // LDS: bisection (aliases the stage-1 and chase region)
@@ -828,7 +828,9 @@ struct Band {
     // then A <- A - V W^T - W V^T with V = [V_p V_p+1], W = [W_p W_p+1] (rank
     // 4 BW) over tile columns >= q + 1.  One read-modify-write of the trailing
     // triangle per pair instead of one per panel.  A last panel without a
-    // partner is updated alone.
+    // partner is updated alone.  (FP64 trailing matrix only: with an FP32
+    // one the update is cheaper than the extra corrections and staging.)
+    static constexpr int PANELS = (sizeof(S) == 8) ? 2 : 1;   // panels whose V and W the slot holds
     __device__ void reduce_to_band() {
         int k0 = 0;
         while (k0 < m) {
@@ -848,7 +850,7 @@ struct Band {
             make_w(J1, r0);
             __syncthreads();
             EEID_PHASE_MARK(clk, 3);
-            const bool pair = (k0 % TILE == 0) && (r0 + BW < m);
+            const bool pair = PANELS == 2 && (k0 % TILE == 0) && (r0 + BW < m);
             syr2k<BW>(J1, pair ? J1 + 1 : T, V0, W0);
             __syncthreads();
             EEID_PHASE_MARK(clk, 4);
@@ -876,7 +878,7 @@ struct Band {
             make_w(J2, r1);
             __syncthreads();
             EEID_PHASE_MARK(clk, 3);
-            syr2k<2 * BW>(J2, T, V0, W0);
+            if constexpr (PANELS == 2) syr2k<2 * BW>(J2, T, V0, W0);
             __syncthreads();
             EEID_PHASE_MARK(clk, 4);
             k0 = r1;
@@ -1335,7 +1337,7 @@ template <class S>
 __host__ __device__ inline int64_t slot_bytes_band(int LDmax) {
     const int64_t T = LDmax / TILE;
     const int64_t tiles = T * (T + 1) / 2 * TILE_ELEMS * (int64_t)sizeof(S);
-    const int64_t panel = 4 * (int64_t)BW * LDmax * 8;   // V and W of a pair of panels
+    const int64_t panel = 2 * (int64_t)Band<S, 256>::PANELS * BW * LDmax * 8;   // V and W (one panel or a pair)
     const int64_t band = (int64_t)(LDmax + BW) * BLD * 8;
     const int64_t de = 2 * (int64_t)LDmax * 8;
     return ((tiles + 255) / 256) * 256 + panel + band + de;
@@ -1403,10 +1405,10 @@ void band_bisect_kernel(TriArgs args) {
         const int64_t T = t.T;
         const int64_t tile_bytes = ((T * (T + 1) / 2 * TILE_ELEMS * (int64_t)sizeof(S) + 255) / 256) * 256;
         t.V0 = reinterpret_cast<double *>(slot + tile_bytes);
-        t.W0 = t.V0 + (int64_t)2 * BW * t.LD;
+        t.W0 = t.V0 + (int64_t)Band<S, NT>::PANELS * BW * t.LD;
         t.V = t.V0;
         t.Wm = t.W0;
-        t.bnd = t.W0 + (int64_t)2 * BW * t.LD;
+        t.bnd = t.W0 + (int64_t)Band<S, NT>::PANELS * BW * t.LD;
         t.dg = t.bnd + (int64_t)BLD * (t.LD + BW);
         t.eg = t.dg + t.LD;
         if (it.m <= Band<S, NT>::SMALL_MAX) {

@@ -288,6 +288,50 @@ struct Panel {
 // count there could only have said what the bracket says.  So a minor's
 // eigenvalues have the same bits whether or not its matrix's eigenvalues
 // were ready when it started.
+// Sturm counts at S points x[t] on the (d_i, e_{i-1}^2) pairs in LDS (de, 2m
+// doubles): cnt[t] = #{i : q_i < 0}.  EXACT: e^2 / q by correctly rounded
+// division; else e^2 times the hardware reciprocal refined by one Newton
+// step.  With few points per lane, four (or two) steps at a time with their
+// LDS loads issued first (the loop is otherwise bound by the LDS latency of
+// every step); the arithmetic of each point is the same sequence either way.
+typedef const __attribute__((address_space(3))) double lds_cdouble;
+template <int S, bool EXACT>
+__device__ __forceinline__ void sturm_counts(const double *de, int m, const double (&x)[S], int (&cnt)[S],
+                                             double pivmin) {
+    lds_cdouble *dl = (lds_cdouble *)de;
+    double q[S];
+#pragma unroll
+    for (int t = 0; t < S; ++t) { q[t] = 1.0; cnt[t] = 0; }
+    auto step = [&](double d, double e2) {
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            double v;
+            if constexpr (EXACT) {
+                v = (d - x[t]) - e2 / q[t];
+            } else {
+                double r = __builtin_amdgcn_rcp(q[t]);
+                r = fma(fma(-q[t], r, 1.0), r, r);
+                v = (d - x[t]) - e2 * r;
+            }
+            v = (fabs(v) < pivmin) ? -pivmin : v;   // |q| >= pivmin keeps e2 / q finite
+            cnt[t] += (v < 0.0) ? 1 : 0;
+            q[t] = v;
+        }
+    };
+    constexpr int U = (S <= 2) ? 4 : ((S <= 4) ? 2 : 1);   // eight points hide the latency by themselves
+    int i = 0;
+    if constexpr (U > 1) {
+        for (; i + U <= m; i += U) {
+            double d[U], e2[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) { d[u] = dl[2 * (i + u)]; e2[u] = dl[2 * (i + u) + 1]; }
+#pragma unroll
+            for (int u = 0; u < U; ++u) step(d[u], e2[u]);
+        }
+    }
+    for (; i < m; ++i) step(dl[2 * i], dl[2 * i + 1]);
+}
+
 template <int NT, int S>
 __device__ void bisect_block(int base, int ie, int m, const double *de, double *out, int tid, double gl,
                              double gu, double pad, double pivmin, double atol, const double *brk) {
@@ -303,26 +347,7 @@ __device__ void bisect_block(int base, int ie, int m, const double *de, double *
     }
     // Sturm counts at S points; EXACT: correctly rounded division
     auto counts = [&](const double (&x)[S], int (&cnt)[S], auto exact) {
-        double q[S];
-#pragma unroll
-        for (int t = 0; t < S; ++t) { q[t] = 1.0; cnt[t] = 0; }
-        for (int i = 0; i < m; ++i) {
-            const double d = de[2 * i], e2 = de[2 * i + 1];
-#pragma unroll
-            for (int t = 0; t < S; ++t) {
-                double v;
-                if constexpr (decltype(exact)::value) {
-                    v = (d - x[t]) - e2 / q[t];
-                } else {
-                    double r = __builtin_amdgcn_rcp(q[t]);
-                    r = fma(fma(-q[t], r, 1.0), r, r);
-                    v = (d - x[t]) - e2 * r;
-                }
-                v = (fabs(v) < pivmin) ? -pivmin : v;   // |q| >= pivmin keeps e2 / q finite
-                cnt[t] += (v < 0.0) ? 1 : 0;
-                q[t] = v;
-            }
-        }
+        sturm_counts<S, decltype(exact)::value>(de, m, x, cnt, pivmin);
     };
     const std::integral_constant<bool, false> fast{};
     const std::integral_constant<bool, true> exact{};
@@ -448,23 +473,10 @@ __device__ void multisect_small(int m, const double *de, double *out, int tid, i
     const unsigned long long gmask = (1ull << L) - 1;
     double lo = gl, hi = gu;
     auto count1 = [&](double x, auto exact) {
-        double q = 1.0;
-        int cnt = 0;
-        for (int i = 0; i < m; ++i) {
-            const double d = de[2 * i], e2 = de[2 * i + 1];
-            double v;
-            if constexpr (decltype(exact)::value) {
-                v = (d - x) - e2 / q;
-            } else {
-                double r = __builtin_amdgcn_rcp(q);
-                r = fma(fma(-q, r, 1.0), r, r);
-                v = (d - x) - e2 * r;
-            }
-            v = (fabs(v) < pivmin) ? -pivmin : v;
-            cnt += (v < 0.0) ? 1 : 0;
-            q = v;
-        }
-        return cnt;
+        const double xs[1] = {x};
+        int cnt[1];
+        sturm_counts<1, decltype(exact)::value>(de, m, xs, cnt, pivmin);
+        return cnt[0];
     };
     const std::integral_constant<bool, false> fast{};
     const std::integral_constant<bool, true> exact{};
