@@ -7,7 +7,21 @@ import numpy as np
 
 
 def announce(msg: str) -> None:
-    print(f"[gpu-case] {msg}", flush=True)
+    """Print a progress line that reaches the terminal while the test runs,
+    also under pytest's output capture (long GPU cases stay visibly alive)."""
+    line = f"[gpu-case] {msg}"
+    capman = None
+    try:
+        from tests import conftest
+        if conftest.CONFIG is not None:
+            capman = conftest.CONFIG.pluginmanager.getplugin("capturemanager")
+    except Exception:
+        capman = None
+    if capman is not None:
+        with capman.global_and_fixture_disabled():
+            print(line, flush=True)
+    else:
+        print(line, flush=True)
     sys.stdout.flush()
 
 
