@@ -170,11 +170,15 @@ def errors(mats, truth, lam, mu, V2, n):
     return out
 
 
-def run_form(mats_dev, n, form, steps, warmup, tune=True):
+def run_form(mats_dev, n, form, steps, warmup, tune=True, graph=True):
+    """Warm-up (including the recording of the graphs), then `steps` timed
+    steps: the eigenvalue launch and the identity launch, each a hipGraph
+    replay in graph mode (the batch packed and the outputs allocated once, so
+    every step replays the same recording), with HIP events on the stream
+    around each."""
     import torch
     from paper_2002_04989_amd import eeid
     stream = torch.cuda.current_stream()
-    res = None
     tuned = None
     if isinstance(tune, str):  # a configuration given on the command line
         eeid.set_variant(tune)
@@ -182,24 +186,40 @@ def run_form(mats_dev, n, form, steps, warmup, tune=True):
     elif tune:  # untimed: pick the fastest kernel configuration for this batch
         tuned = eeid.autotune(mats_dev, form)
         log(f"{form}: autotune chose {tuned[0]} ({tuned[1]:.0f} ms)")
-    for _ in range(warmup):
-        res = eeid.all_components(mats_dev, form)
-    torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
-           torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(steps):
-        e0, e1, e2 = ev[k]
-        e0.record(stream)
-        lam, mu, flags = eeid.minor_eigvals(mats_dev, form)     # the dominant (persistent) kernel
-        e1.record(stream)
-        V2 = eeid.components(lam, mu, n, flags)
-        e2.record(stream)
-        res = (lam, mu, V2, flags)
-        log(f"{form}: step {k + 1}/{steps} enqueued")
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    packed = eeid.pack(mats_dev)
+    nl, nm, nv = eeid.sizes(n)
+    dev = packed.flat.device
+    lam = torch.empty(nl, dtype=torch.float64, device=dev)
+    mu = torch.empty(max(nm, 1), dtype=torch.float64, device=dev)
+    flags = torch.empty(len(n), dtype=torch.int32, device=dev)
+    V2 = torch.empty(nv, dtype=torch.float64, device=dev)
+
+    def step():
+        eeid.minor_eigvals(packed, form, out=(lam, mu, flags))
+        eeid.components(lam, mu[:nm], n, flags, out=V2)
+
+    eeid.set_graph_mode(graph)
+    try:
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+               torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            e0, e1, e2 = ev[k]
+            e0.record(stream)
+            eeid.minor_eigvals(packed, form, out=(lam, mu, flags))     # the dominant (persistent) kernel
+            e1.record(stream)
+            eeid.components(lam, mu[:nm], n, flags, out=V2)
+            e2.record(stream)
+            log(f"{form}: step {k + 1}/{steps} enqueued")
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    finally:
+        eeid.set_graph_mode(False)
+    res = (lam, mu[:nm], V2, flags)
     tri_ms = sum(e0.elapsed_time(e1) for e0, e1, _ in ev) / steps
     id_ms = sum(e1.elapsed_time(e2) for _, e1, e2 in ev) / steps
     step_ms = sorted(e0.elapsed_time(e2) for e0, _, e2 in ev)
@@ -359,14 +379,13 @@ def other_workloads(steps=(20, 3, 2)):
         n = [m.shape[0] for m in mats]
         dev = [torch.from_numpy(m).to("cuda:0") for m in mats]
         torch.cuda.synchronize()
-        graph = name == "uneven256"
-        if graph:
-            eeid.set_graph_mode(True)
+        autotuned = name == "uneven256"
         try:
-            res, wall, tri, idn, tuned, spread = run_form(dev, n, "fp64", nsteps, 1, tune=graph)
+            res, wall, tri, idn, tuned, spread = run_form(dev, n, "fp64", nsteps, 1, tune=autotuned)
+            # the same steps launched eagerly, for comparison (launch overhead matters at n = 64)
+            _, _, _, _, _, spread_eager = run_form(dev, n, "fp64", nsteps, 0, tune=False, graph=False)
         finally:
-            if graph:
-                eeid.set_graph_mode(False)
+            if autotuned:
                 eeid.set_variant(None)
         lam = eeid.split(res[0].cpu().numpy(), n, "lambda")
         mu = eeid.split(res[1].cpu().numpy(), n, "mu")
@@ -378,8 +397,9 @@ def other_workloads(steps=(20, 3, 2)):
                "value": comps / (spread["median"] * 1e-3), "unit": "components/s",
                "eigenvalue_kernel_ms": round(tri, 3), "identity_ms": round(idn, 3),
                "flags_nonzero": int(sum(1 for f in flags if f))}
-        if graph:
-            row["launch"] = "hipGraph replay"
+        row["launch"] = "hipGraph replay"
+        row["eager_ms_per_step"] = round(spread_eager["median"], 3)
+        if autotuned:
             row["variant"] = tuned[0] if tuned else None
         if name == "uneven256":
             g = load_golden(name)
@@ -573,6 +593,7 @@ def main():
         "metric": METRIC, "value": value, "unit": "components/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 2), "step_ms": spread64,
         "end_to_end_ms_incl_h2d_d2h": round(e2e64, 2), "higher_is_better": True, "scaling": "weak",
+        "launch": "hipGraph replays (the eigenvalue launch and the identity launch, each recorded once)",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "n2048 pair: GOE (seed 4) + 16-cluster Q diag(lam) Q^T (seed 40); eigenvalues of "
                                "both matrices and all 2x2048 minors in one persistent launch, then all 2x2048^2 "

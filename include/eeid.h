@@ -98,7 +98,9 @@ eeid_status_t eeid_create(eeid_handle_t *h, int hip_device);
 eeid_status_t eeid_destroy(eeid_handle_t h);
 
 /* Make subsequent calls enqueue on `stream` (a hipStream_t of the handle's
- * device, passed as void*; NULL = null stream). */
+ * device, passed as void*; NULL = null stream).  When the stream changes,
+ * the work already queued on the previous one is waited for first (the
+ * handle's workspace is shared by all its calls). */
 eeid_status_t eeid_set_stream(eeid_handle_t h, void *stream);
 
 /* Static description of a status code (never NULL). */
@@ -248,8 +250,7 @@ eeid_status_t eeid_signed_eigenvectors(eeid_handle_t h, eeid_dtype_t t, int64_t 
 /* eeid_minor_eigvals followed by eeid_components: every |v_ij|^2 of every
  * matrix of the batch from device-resident A to device-resident V2.  In graph
  * mode (eeid_set_graph_mode) the launches are recorded once per argument set
- * into a hipGraph and replayed on a private stream ordered after, and before,
- * the handle's stream. */
+ * into a hipGraph and replayed on the handle's stream. */
 eeid_status_t eeid_all_components(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p,
                                   int64_t count, const int64_t *n, const int64_t *a_offset,
                                   const void *A, double *lambda, double *mu, double *V2,
@@ -271,7 +272,14 @@ eeid_status_t eeid_all_components(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p
 typedef enum { EEID_IDENTITY_PRODUCTS = 0, EEID_IDENTITY_PAIRED = 1 } eeid_identity_form_t;
 eeid_status_t eeid_set_identity_form(eeid_handle_t h, int form);
 
-/* Enable (1) or disable (0) graph mode for eeid_all_components. */
+/* Enable (1) or disable (0) graph mode for eeid_minor_eigvals,
+ * eeid_components and eeid_all_components: each call's launches are recorded
+ * into a hipGraph the first time an argument set (entry point, pointers,
+ * orders, kernel configuration) is seen (recording on a private stream) and
+ * replayed afterwards on the handle's stream.  Up to eight
+ * recorded argument sets are kept per handle (least recently used replaced);
+ * reallocation of the handle's buffers invalidates them.  Results are the
+ * same as in eager mode. */
 eeid_status_t eeid_set_graph_mode(eeid_handle_t h, int enable);
 
 /* Phase timers of the two-stage kernel, in builds compiled with

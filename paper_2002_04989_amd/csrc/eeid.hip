@@ -79,9 +79,8 @@ struct eeid_handle_s {
     // graph mode
     bool graph_mode = false;
     hipStream_t gstream = nullptr;
-    hipEvent_t ev_in = nullptr, ev_out = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    std::vector<int64_t> gkey;
+    struct Graph { std::vector<int64_t> key; hipGraphExec_t exec; };
+    std::vector<Graph> graphs;   // recorded launches, least recently used first (at most GRAPH_CACHE)
     // tune table: {dtype, prec, n_max, problems, variant}
     std::vector<std::array<int64_t, 5>> tune;
     std::string tune_path;
@@ -401,19 +400,28 @@ eeid_status_t run_now(eeid_handle_t h, const Enqueue &e) {
     return EEID_OK;
 }
 
-// Record (once per key) and replay the enqueue steps as one hipGraph on the
-// handle's private stream, ordered after and before the caller's stream.
+// Record (once per key, on the handle's private stream) and replay the
+// enqueue steps as one hipGraph on the handle's stream.
+// Up to GRAPH_CACHE recorded launches are kept per handle (a key names the
+// entry point, its pointers and sizes, the kernel configuration and the
+// generation of the handle's buffers), the least recently used replaced.
+constexpr size_t GRAPH_CACHE = 8;
 eeid_status_t run_graph(eeid_handle_t h, const std::vector<int64_t> &key, const std::vector<Enqueue> &steps) {
     if (!h->gstream) {
         HIP_TRY(h, hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
-        HIP_TRY(h, hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
-        HIP_TRY(h, hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming));
     }
-    if (!h->gexec || key != h->gkey) {
-        if (h->gexec) {
-            HIP_TRY(h, hipStreamSynchronize(h->gstream));
-            HIP_TRY(h, hipGraphExecDestroy(h->gexec));
-            h->gexec = nullptr;
+    size_t at = h->graphs.size();
+    for (size_t i = 0; i < h->graphs.size(); ++i)
+        if (h->graphs[i].key == key) at = i;
+    if (at < h->graphs.size()) {
+        eeid_handle_s::Graph g = std::move(h->graphs[at]);
+        h->graphs.erase(h->graphs.begin() + (std::ptrdiff_t)at);
+        h->graphs.push_back(std::move(g));
+    } else {
+        if (h->graphs.size() >= GRAPH_CACHE) {
+            HIP_TRY(h, hipStreamSynchronize(h->stream));   // its last replay has ended
+            HIP_TRY(h, hipGraphExecDestroy(h->graphs.front().exec));
+            h->graphs.erase(h->graphs.begin());
         }
         hipGraph_t g = nullptr;
         HIP_TRY(h, hipStreamBeginCapture(h->gstream, hipStreamCaptureModeThreadLocal));
@@ -426,19 +434,16 @@ eeid_status_t run_graph(eeid_handle_t h, const std::vector<int64_t> &key, const 
             return fail(h, EEID_ERR_HIP, std::string("graph capture failed: ") +
                                              hipGetErrorString(err != hipSuccess ? err : err2));
         }
-        hipError_t err3 = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+        hipGraphExec_t exec = nullptr;
+        hipError_t err3 = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
-        if (err3 != hipSuccess) {
-            h->gexec = nullptr;
+        if (err3 != hipSuccess)
             return fail(h, EEID_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(err3));
-        }
-        h->gkey = key;
+        h->graphs.push_back({key, exec});
     }
-    HIP_TRY(h, hipEventRecord(h->ev_in, h->stream));
-    HIP_TRY(h, hipStreamWaitEvent(h->gstream, h->ev_in, 0));
-    HIP_TRY(h, hipGraphLaunch(h->gexec, h->gstream));
-    HIP_TRY(h, hipEventRecord(h->ev_out, h->gstream));
-    HIP_TRY(h, hipStreamWaitEvent(h->stream, h->ev_out, 0));
+    // replayed on the handle's stream itself (ordered with the caller's work,
+    // no cross-stream events); the private stream only records
+    HIP_TRY(h, hipGraphLaunch(h->graphs.back().exec, h->stream));
     return EEID_OK;
 }
 
@@ -509,9 +514,7 @@ eeid_status_t eeid_destroy(eeid_handle_t h) {
     (void)hipSetDevice(h->device);
     (void)hipStreamSynchronize(h->stream);
     if (h->gstream) (void)hipStreamSynchronize(h->gstream);
-    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
-    if (h->ev_in) (void)hipEventDestroy(h->ev_in);
-    if (h->ev_out) (void)hipEventDestroy(h->ev_out);
+    for (const auto &g : h->graphs) (void)hipGraphExecDestroy(g.exec);
     if (h->gstream) (void)hipStreamDestroy(h->gstream);
     Buf *bufs[] = {&h->work,     &h->items,     &h->desc,    &h->desc_sub, &h->dpair, &h->dpair_sub,
                    &h->lam_ready, &h->sbuf, &h->lat_work, &h->lat_items, &h->lat_bar};
@@ -524,7 +527,14 @@ eeid_status_t eeid_destroy(eeid_handle_t h) {
 
 eeid_status_t eeid_set_stream(eeid_handle_t h, void *stream) {
     if (!h) return EEID_ERR_INVALID_ARG;
-    h->stream = reinterpret_cast<hipStream_t>(stream);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (st != h->stream) {
+        // work queued on the previous stream ends before the handle's buffers
+        // (and recorded graphs) are used from the new one
+        HIP_TRY(h, hipSetDevice(h->device));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+    }
+    h->stream = st;
     return EEID_OK;
 }
 
@@ -605,8 +615,15 @@ eeid_status_t eeid_minor_eigvals(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p,
     for (int64_t b = 0; b < count; ++b) need_mu = need_mu || n[b] >= 2;
     if (need_mu && !mu) return fail(h, EEID_ERR_INVALID_ARG, "mu is null");
     Enqueue e;
-    s = prepare_eigs(h, t, p, count, n, a_offset, A, lambda, mu, flags, 1, 0, nullptr, &e);
-    return s != EEID_OK ? s : run_now(h, e);
+    int variant = 0;
+    s = prepare_eigs(h, t, p, count, n, a_offset, A, lambda, mu, flags, 1, 0, nullptr, &e, &variant);
+    if (s != EEID_OK) return s;
+    if (!h->graph_mode) return run_now(h, e);
+    std::vector<int64_t> key = {1, (int64_t)t, (int64_t)p, count, (int64_t)(intptr_t)A, (int64_t)(intptr_t)lambda,
+                                (int64_t)(intptr_t)mu, (int64_t)(intptr_t)flags, (int64_t)h->generation,
+                                (int64_t)variant};
+    for (int64_t b = 0; b < count; ++b) { key.push_back(n[b]); key.push_back(a_offset[b]); }
+    return run_graph(h, key, {e});
 }
 
 eeid_status_t eeid_minor_eigvals_subset(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64_t n,
@@ -707,7 +724,12 @@ eeid_status_t eeid_components(eeid_handle_t h, int64_t count, const int64_t *n, 
     if (!h) return EEID_ERR_INVALID_ARG;
     Enqueue e;
     eeid_status_t s = prepare_components(h, count, n, lambda, mu, V2, flags, &e);
-    return s != EEID_OK ? s : run_now(h, e);
+    if (s != EEID_OK) return s;
+    if (!h->graph_mode) return run_now(h, e);
+    std::vector<int64_t> key = {2, count, (int64_t)(intptr_t)lambda, (int64_t)(intptr_t)mu, (int64_t)(intptr_t)V2,
+                                (int64_t)(intptr_t)flags, (int64_t)h->generation, (int64_t)h->identity_form};
+    for (int64_t b = 0; b < count; ++b) key.push_back(n[b]);
+    return run_graph(h, key, {e});
 }
 
 eeid_status_t eeid_components_noalloc(eeid_handle_t h, int64_t count, const int64_t *n, const double *lambda,
@@ -859,7 +881,7 @@ eeid_status_t eeid_all_components(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p
         s = run_now(h, e1);
         return s != EEID_OK ? s : run_now(h, e2);
     }
-    std::vector<int64_t> key = {(int64_t)t, (int64_t)p, count, (int64_t)(intptr_t)A, (int64_t)(intptr_t)lambda,
+    std::vector<int64_t> key = {3, (int64_t)t, (int64_t)p, count, (int64_t)(intptr_t)A, (int64_t)(intptr_t)lambda,
                                 (int64_t)(intptr_t)mu, (int64_t)(intptr_t)V2, (int64_t)(intptr_t)flags,
                                 (int64_t)h->generation, (int64_t)variant, (int64_t)h->identity_form};
     for (int64_t b = 0; b < count; ++b) { key.push_back(n[b]); key.push_back(a_offset[b]); }

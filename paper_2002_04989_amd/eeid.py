@@ -131,9 +131,23 @@ def _dtype_code(A):
     raise TypeError(f"A must be float64 or complex128, got {A.dtype}")
 
 
+class Packed:
+    """A batch packed once (one flat device buffer, orders, offsets), so that
+    repeated calls pass the same pointers (graph mode replays them)."""
+
+    def __init__(self, flat, n, offs):
+        self.flat, self.n, self.offs = flat, n, offs
+
+
+def pack(mats) -> Packed:
+    return Packed(*_batch(mats))
+
+
 def _batch(mats):
-    """Accept one square tensor or a list of them; returns (flat, n, offsets)."""
+    """Accept one square tensor, a list of them or a Packed batch; returns (flat, n, offsets)."""
     import torch
+    if isinstance(mats, Packed):
+        return mats.flat, mats.n, mats.offs
     if isinstance(mats, torch.Tensor):
         mats = [mats]
     n = [int(m.shape[0]) for m in mats]
@@ -168,15 +182,19 @@ def eigvalsh_batched(mats, prec: str = "fp64"):
     return lam, flags
 
 
-def minor_eigvals(mats, prec: str = "fp64"):
-    """lambda(A_b) and the spectra of all minors: (lambda [sum n], mu [sum n(n-1)], flags)."""
+def minor_eigvals(mats, prec: str = "fp64", out=None):
+    """lambda(A_b) and the spectra of all minors: (lambda [sum n], mu [sum n(n-1)], flags).
+    out: optional (lambda, mu, flags) tensors to write into (mu of at least one element)."""
     import torch
     flat, n, offs = _batch(mats)
     dev = flat.device
     nl, nm, _ = sizes(n)
-    lam = torch.empty(nl, dtype=torch.float64, device=dev)
-    mu = torch.empty(max(nm, 1), dtype=torch.float64, device=dev)
-    flags = torch.empty(len(n), dtype=torch.int32, device=dev)
+    if out is not None:
+        lam, mu, flags = out
+    else:
+        lam = torch.empty(nl, dtype=torch.float64, device=dev)
+        mu = torch.empty(max(nm, 1), dtype=torch.float64, device=dev)
+        flags = torch.empty(len(n), dtype=torch.int32, device=dev)
     h = handle(dev.index)
     _check(load_library().eeid_minor_eigvals(h, _dtype_code(flat), PREC[prec], len(n), _i64(n), _i64(offs),
                                               flat.data_ptr(), lam.data_ptr(), mu.data_ptr(), flags.data_ptr()), h)
@@ -227,11 +245,12 @@ def component_column(A, j: int):
     return W[:, 0], lam, mu[0], flag
 
 
-def components(lam, mu, n: Sequence[int], flags):
-    """V2 [sum n^2] with V2_b[i*n_b + j] = |v_ij|^2 (Eq. (2)); updates flags in place."""
+def components(lam, mu, n: Sequence[int], flags, out=None):
+    """V2 [sum n^2] with V2_b[i*n_b + j] = |v_ij|^2 (Eq. (2)); updates flags in place.
+    out: optional V2 tensor to write into."""
     import torch
     n = [int(k) for k in n]
-    V2 = torch.empty(sizes(n)[2], dtype=torch.float64, device=lam.device)
+    V2 = out if out is not None else torch.empty(sizes(n)[2], dtype=torch.float64, device=lam.device)
     h = handle(lam.device.index)
     _check(load_library().eeid_components(h, len(n), _i64(n), lam.data_ptr(),
                                            mu.data_ptr() if mu.numel() else None, V2.data_ptr(),

@@ -6,7 +6,7 @@ full-size GPU tests compare the library against these on the same seeded
 inputs (regenerated from paper_2002_04989_amd.inputs, which is deterministic).
 
     python tests/golden/make_golden.py [--threads T] [goe2048] [clustered2048] [gue4096]
-                                       [goe64] [goe512] [uneven256]
+                                       [goe64] [goe512] [uneven256] [goe4700]
 
 The n = 2048 workloads use the extended-precision Jacobi (the default
 oracle; about 25 min per eigenvalue problem on one core): its eigenvalue
@@ -17,9 +17,11 @@ tiny gaps).  All eigenvalue problems of all requested workloads share one
 thread pool, longest first.
 
 The smaller workloads (GOE n = 64 with all of its minors, GOE n = 512 with
-six, and five members of the uneven batch of 256 with three minors each)
+six, and six members of the uneven batch of 256 with three minors each)
 take seconds to a minute and let the benchmark state every configuration's
-error against the oracle without running it.
+error against the oracle without running it.  goe4700 (the largest real
+order in the GPU tests: lambda(A) and minors 0 and 2351) uses the double
+precision Jacobi, about half an hour per problem.
 
 Output: tests/golden/<name>.npz (arrays js, lam, mu, W, flags; for a batch
 workload the same arrays suffixed _<member> plus ``members``) and
@@ -72,6 +74,7 @@ WORKLOADS = {
     "goe64": lambda: (inputs.make_config(1)[0], list(range(64)), "jacobi", 3e-5),
     "goe512": lambda: (inputs.make_config(2)[0], [0, 1, 100, 255, 256, 511], "jacobi", 1.6e-2),
     "uneven256": lambda: (uneven_members(), None, "jacobi", 5e-3),
+    "goe4700": lambda: (inputs.goe(4700, 47), [0, 2351], "jacobi64", 1.5),
 }
 
 

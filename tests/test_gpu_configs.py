@@ -175,10 +175,14 @@ def test_pair2048_fp32_trailing(pair2048, variant):
         print(f"{name} fp32 form: max|dlam|/||A||={dl:.2e} max|dmu|/||A||={dm:.2e}")
         bound = 8 * np.sqrt(2048) * 2.0 ** -24          # a-priori eigenvalue perturbation
         assert dl < bound and dm < bound
+        # the stated bounds of this form: the measured errors (GOE 1.6e-8 / 2.5e-8,
+        # clustered 3.8e-8 / 4.6e-8 relative to ||A||) with a margin of about 20
+        assert dl < 1e-6 and dm < 1e-6
         colsum = np.max(np.abs(W.sum(axis=0) - 1))
         if name == "goe2048":
-            assert colsum < 1e-3
-            assert np.max(np.abs(W[:, js] - g["W"])) < 1e-4
+            # measured: column sums 2.7e-6, sampled W 7.9e-7
+            assert colsum < 3e-5
+            assert np.max(np.abs(W[:, js] - g["W"])) < 1e-5
         else:
             # individual vectors inside a cluster are not resolved at FP32 (gap 1e-6 < error);
             # the projector onto each cluster is
@@ -186,7 +190,8 @@ def test_pair2048_fp32_trailing(pair2048, variant):
             cl = W.reshape(16, 128, 2048).sum(axis=1) - W_exact.reshape(16, 128, 2048).sum(axis=1)
             print(f"clustered fp32: max|dW|={d.max():.2e} cluster projector err={np.abs(cl).max():.2e} "
                   f"column-sum residual={colsum:.2e}")
-            assert d.max() < 1e-2 and np.abs(cl).max() < 1e-2 and colsum < 1e-2
+            # measured: max|dW| 8.4e-4, projector 1.4e-3, column sums 3.2e-3
+            assert d.max() < 5e-3 and np.abs(cl).max() < 1e-2 and colsum < 2e-2
 
 
 @pytest.mark.parametrize("form", ["fp64", "fp32"])

@@ -386,6 +386,54 @@ def test_graph_mode_replays_match_eager():
         eeid.set_graph_mode(False)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_graph_mode_separate_entry_points(prec):
+    """Graph mode for eeid_minor_eigvals and eeid_components called one after
+    the other (two recordings in the handle's cache), as the benchmark times
+    them: four replays of each, with eager work, clobbered outputs and another
+    batch's recording in between, every replay bit for bit the eager result."""
+    import torch
+    from paper_2002_04989_amd import eeid
+    mats = [inputs.goe(200, 15), inputs.wishart(150, 16), inputs.goe(40, 17)]
+    other = [inputs.goe(90, 18)]
+    announce(f"graph mode, separate entry points, {prec}")
+    dev = [torch.from_numpy(m).cuda() for m in mats]
+    dev_other = [torch.from_numpy(m).cuda() for m in other]
+    packed = eeid.pack(dev)
+    n = packed.n
+    nl, nm, nv = eeid.sizes(n)
+    lam0, mu0, fl0 = eeid.minor_eigvals(packed, prec)
+    V20 = eeid.components(lam0, mu0, n, fl0)
+    torch.cuda.synchronize()
+    ref = [lam0.cpu().numpy(), mu0.cpu().numpy(), V20.cpu().numpy(), fl0.cpu().numpy()]
+    lam = torch.empty(nl, dtype=torch.float64, device="cuda")
+    mu = torch.empty(nm, dtype=torch.float64, device="cuda")
+    flags = torch.empty(len(n), dtype=torch.int32, device="cuda")
+    V2 = torch.empty(nv, dtype=torch.float64, device="cuda")
+    eeid.set_graph_mode(True)
+    try:
+        for rep in range(4):
+            eeid.minor_eigvals(packed, prec, out=(lam, mu, flags))
+            eeid.components(lam, mu, n, flags, out=V2)
+            torch.cuda.synchronize()
+            got = [lam.cpu().numpy(), mu.cpu().numpy(), V2.cpu().numpy(), flags.cpu().numpy()]
+            for x, y in zip(got, ref):
+                np.testing.assert_array_equal(x, y, err_msg=f"replay {rep}")
+            lam.fill_(-7.0); V2.zero_(); mu.fill_(3.0); flags.fill_(5)
+            if rep == 1:   # another argument set recorded and replayed in between
+                lo, mo, fo = eeid.minor_eigvals(dev_other, prec)
+                torch.cuda.synchronize()
+                eeid.set_graph_mode(False)
+                le, me, fe = eeid.minor_eigvals(dev_other, prec)
+                eeid.set_graph_mode(True)
+                torch.cuda.synchronize()
+                np.testing.assert_array_equal(lo.cpu().numpy(), le.cpu().numpy())
+            _ = eeid.eigvalsh_batched(dev[2])
+            torch.cuda.synchronize()
+    finally:
+        eeid.set_graph_mode(False)
+
+
 def test_autotune_picks_a_variant_and_results_hold():
     from paper_2002_04989_amd import eeid
     mats = [inputs.goe(130, 8), inputs.goe(64, 9)]
