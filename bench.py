@@ -7,12 +7,18 @@ each matrix and of all 2048 of its minors (one persistent launch over 4098
 problems), then Eq. (2) for all 2 x 2048^2 components.  Inputs are resident
 in HBM before timing starts; outputs stay there.
 
-Prints ONE JSON line.  ``value`` is components/s of the FP64 form; the FP32
-trailing-update form is timed the same way and reported in ``fp32_form``;
-each form's error against the FP64 oracle (sampled minors) and, for the
-clustered matrix, against the exact answer (Q**2)^T is reported.
+Prints ONE JSON line.  ``value`` is components/s of the FP64 form, each
+step two hipGraph replays (the eigenvalue launch, then the identity launch);
+the FP32 trailing-update form is timed the same way and reported in
+``fp32_form``; each form's error against the FP64 oracle (sampled minors)
+and, for the clustered matrix, against the exact answer (Q**2)^T is
+reported.  ``other_workloads`` times the n=64, n=512 and uneven-batch
+workloads (whole path, errors against stored oracle values) and one wave of
+the complex n=4096 job; ``single_component_latency`` the paper's Table 1
+regime; ``cpu_baseline`` the oracle on this host.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--copy-ref]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-fp32] [--no-paired]
+                    [--no-latency] [--no-others] [--no-tune | --variant V] [--copy-ref]
 """
 from __future__ import annotations
 
@@ -415,6 +421,52 @@ def other_workloads(steps=(20, 3, 2)):
     return out
 
 
+def complex4096(reps=2, extra=251):
+    """Complex Hermitian n = 4096 (GUE seed 5), both forms: one launch of
+    lambda(A) and 255 minors (the four with stored oracle values and 251
+    seeded others) -- one problem per resident workgroup slot (256, one per
+    CU), i.e. one wave of the 4097-problem job -- timed with HIP events (best
+    of `reps`), errors against the stored oracle values, and the time scaled
+    by the 17 waves the full job needs on the same slots (16 full ones and
+    one problem).  The full job is run in the GPU tests, not here: it takes
+    minutes."""
+    import numpy as np
+    import torch
+    from paper_2002_04989_amd import eeid, inputs
+    g = load_golden("gue4096")
+    A = inputs.gue(4096, 5)
+    n = A.shape[0]
+    stored = [int(j) for j in g["js"]] if g is not None else []
+    rng = np.random.default_rng(4096)
+    rest = [int(j) for j in rng.choice(np.setdiff1d(np.arange(n), stored), size=extra, replace=False)]
+    js = sorted(stored + rest)
+    dA = torch.from_numpy(A).to("cuda:0")
+    out = {"workload": "GUE n=4096 (seed 5): lambda(A) + 255 minors in one launch", "problems": len(js) + 1}
+    waves = -(-(n + 1) // (len(js) + 1))
+    for form in ("fp64", "fp32"):
+        times = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(torch.cuda.current_stream())
+            lam, mu, flag = eeid.minor_eigvals_subset(dA, js, prec=form)
+            e1.record(torch.cuda.current_stream())
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        ms = min(times)
+        row = {"dtype": "c128" if form == "fp64" else "c64 trailing / f64 rest", "ms_per_launch": round(ms, 1),
+               "scaled_s_all_4097_problems": round(ms * waves / 1e3, 1),
+               "scaled_components_per_s": n * n / (ms * waves / 1e3), "flag": int(flag.cpu()[0])}
+        if g is not None:
+            lam_h, mu_h = lam.cpu().numpy(), mu.cpu().numpy()
+            s = float(np.max(np.abs(g["lam"])))
+            sel = [js.index(j) for j in stored]
+            row["max_abs_dlam_rel"] = float(np.max(np.abs(lam_h - g["lam"])) / s)
+            row["max_abs_dmu_rel_stored_minors"] = float(np.max(np.abs(mu_h[sel] - g["mu"])) / s)
+        log(f"complex n=4096 {form}: {row['ms_per_launch']} ms for {len(js) + 1} problems")
+        out[form] = row
+    return out
+
+
 # Table 1 of the paper (Section 4): one component of one eigenvector on a 4-core
 # Xeon E3-1270 v6 (NumPy eigh / Algorithm 2, seconds, mean of 10 runs).  Context only.
 PAPER_TABLE1 = {502: (0.170962, 0.119722), 1002: (1.100800, 0.595935), 2002: (9.522480, 3.212001),
@@ -578,6 +630,8 @@ def main():
     if not args.no_others:
         log("smaller workloads")
         others = other_workloads()
+        log("complex n=4096 (one wave of its problems)")
+        others["complex4096"] = complex4096()
     latency = None
     if not args.no_latency:
         log("single-component latency (Table 1 sizes)")
