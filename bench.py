@@ -380,8 +380,8 @@ def other_workloads(steps=(20, 3, 2)):
     import torch
     from paper_2002_04989_amd import eeid, inputs
     out = {}
-    for (name, k, nsteps) in (("goe64", 1, steps[0]), ("goe512", 2, steps[1]), ("uneven256", 3, steps[2])):
-        mats = inputs.make_config(k)
+    for (name, nsteps) in (("goe64", steps[0]), ("goe512", steps[1]), ("uneven256", steps[2])):
+        mats = inputs.make_workload(name)
         n = [m.shape[0] for m in mats]
         dev = [torch.from_numpy(m).to("cuda:0") for m in mats]
         torch.cuda.synchronize()
@@ -548,7 +548,7 @@ def main():
                     help="run a 1 GiB device copy first (reference for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU (asked for --gpus {args.gpus}); "
+        print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}); "
               "the minors shard across GPUs without communication, but no multi-GPU path is built.",
               file=sys.stderr)
         sys.exit(2)

@@ -59,7 +59,7 @@ typedef enum {
     EEID_ERR_NO_DEVICE = 2,    /* no usable GPU, or the device index is out of range */
     EEID_ERR_ALLOC = 3,        /* device workspace could not be allocated */
     EEID_ERR_HIP = 4,          /* a HIP runtime call failed; see eeid_last_error */
-    EEID_ERR_UNSUPPORTED = 5   /* valid request this build does not serve (e.g. n_b too large) */
+    EEID_ERR_UNSUPPORTED = 5   /* valid request this library does not serve (e.g. n_b too large) */
 } eeid_status_t;
 
 typedef enum { EEID_R64 = 0, EEID_C128 = 1 } eeid_dtype_t;

@@ -587,7 +587,7 @@ const char *eeid_status_string(eeid_status_t s) {
         case EEID_ERR_NO_DEVICE: return "EEID_ERR_NO_DEVICE: no usable HIP device";
         case EEID_ERR_ALLOC: return "EEID_ERR_ALLOC: device allocation failed";
         case EEID_ERR_HIP: return "EEID_ERR_HIP: HIP runtime error";
-        case EEID_ERR_UNSUPPORTED: return "EEID_ERR_UNSUPPORTED: request not supported by this build";
+        case EEID_ERR_UNSUPPORTED: return "EEID_ERR_UNSUPPORTED: request not supported by this library";
     }
     return "unknown eeid status";
 }

@@ -29,7 +29,7 @@ import numpy as np
 
 __all__ = [
     "goe", "wishart", "gue", "clustered", "laplacian", "uneven_batch",
-    "pack_batch", "CONFIGS", "make_config",
+    "pack_batch", "WORKLOADS", "make_workload",
 ]
 
 
@@ -137,29 +137,28 @@ def pack_batch(mats):
     return flat, n, offset
 
 
-# The five workloads (sizes, families, precision forms).  ``make_config``
-# builds the matrices; forms are "fp64" (plain) and "fp32" (FP32 trailing
-# storage and FP32 matrix-core trailing update).
-CONFIGS = {
-    1: dict(name="goe64", family="goe", n=64, seed=1, dtype="r64", forms=("fp64",)),
-    2: dict(name="goe512", family="goe", n=512, seed=2, dtype="r64", forms=("fp64",)),
-    3: dict(name="uneven256", family="uneven", count=256, seed=3, dtype="r64", forms=("fp64",)),
-    4: dict(name="goe2048+clustered2048", family="goe+clustered", n=2048, seed=4,
-            dtype="r64", forms=("fp64", "fp32")),
-    5: dict(name="gue4096", family="gue", n=4096, seed=5, dtype="c128", forms=("fp64", "fp32")),
+# The five workloads (sizes, families, precision forms), by name.
+# ``make_workload`` builds the matrices; forms are "fp64" (plain) and "fp32"
+# (FP32 trailing storage and FP32 matrix-core trailing update).
+WORKLOADS = {
+    "goe64": dict(family="goe", n=64, seed=1, dtype="r64", forms=("fp64",)),
+    "goe512": dict(family="goe", n=512, seed=2, dtype="r64", forms=("fp64",)),
+    "uneven256": dict(family="uneven", count=256, seed=3, dtype="r64", forms=("fp64",)),
+    "pair2048": dict(family="goe+clustered", n=2048, seed=4, dtype="r64", forms=("fp64", "fp32")),
+    "gue4096": dict(family="gue", n=4096, seed=5, dtype="c128", forms=("fp64", "fp32")),
 }
 
 
-def make_config(k: int):
-    """Matrices of workload ``k`` (a list; workload 4 holds the GOE and the clustered matrix)."""
-    c = CONFIGS[k]
-    if k in (1, 2):
+def make_workload(name: str):
+    """Matrices of a workload (a list; pair2048 holds the GOE and the clustered matrix)."""
+    c = WORKLOADS[name]
+    if c["family"] == "goe":
         return [goe(c["n"], c["seed"])]
-    if k == 3:
+    if c["family"] == "uneven":
         return uneven_batch(c["count"], 32, 384, c["seed"])
-    if k == 4:
+    if c["family"] == "goe+clustered":
         a_clu, _, _ = clustered(c["n"], 16, 1e-6, 40)
         return [goe(c["n"], c["seed"]), a_clu]
-    if k == 5:
+    if c["family"] == "gue":
         return [gue(c["n"], c["seed"])]
-    raise KeyError(k)
+    raise KeyError(name)

@@ -59,7 +59,7 @@ def uneven_members():
     """Members of the uneven batch checked against the oracle: the two
     smallest, the median, the largest and the first (GOE) and second
     (Wishart) member, each on minors 0, n // 3 and n - 1."""
-    mats = inputs.make_config(3)
+    mats = inputs.make_workload("uneven256")
     order = np.argsort([m.shape[0] for m in mats], kind="stable")
     picks = sorted(set(int(b) for b in (order[0], order[1], order[len(order) // 2], order[-1], 0, 1)))
     return [(b, mats[b], [0, mats[b].shape[0] // 3, mats[b].shape[0] - 1]) for b in picks]
@@ -71,8 +71,8 @@ WORKLOADS = {
     "goe2048": lambda: (inputs.goe(2048, 4), sample_js(2048, 4040, 12), "jacobi", 1.0),
     "clustered2048": lambda: (inputs.clustered(2048, 16, 1e-6, 40)[0], sample_js(2048, 4041, 12), "jacobi", 1.0),
     "gue4096": lambda: (inputs.gue(4096, 5), sample_js(4096, 5050, 0), "jacobi64", 2.2),
-    "goe64": lambda: (inputs.make_config(1)[0], list(range(64)), "jacobi", 3e-5),
-    "goe512": lambda: (inputs.make_config(2)[0], [0, 1, 100, 255, 256, 511], "jacobi", 1.6e-2),
+    "goe64": lambda: (inputs.make_workload("goe64")[0], list(range(64)), "jacobi", 3e-5),
+    "goe512": lambda: (inputs.make_workload("goe512")[0], [0, 1, 100, 255, 256, 511], "jacobi", 1.6e-2),
     "uneven256": lambda: (uneven_members(), None, "jacobi", 5e-3),
     "goe4700": lambda: (inputs.goe(4700, 47), [0, 2351], "jacobi64", 1.5),
 }

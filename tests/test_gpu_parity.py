@@ -41,7 +41,7 @@ def test_goe_sizes(n):
 
 def test_config1_goe64_exhaustive():
     announce("config goe64 exhaustive")
-    A = inputs.make_config(1)[0]
+    A = inputs.make_workload("goe64")[0]
     err = check(A, run_all([A])[0])
     print(f"goe64 max|dW| = {err:.3e}")
 

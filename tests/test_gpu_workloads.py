@@ -65,7 +65,7 @@ def check_invariants(A, lam, W, tol_sum=1e-10):
 
 
 def test_goe512_all_minors():
-    A = inputs.make_config(2)[0]
+    A = inputs.make_workload("goe512")[0]
     n = A.shape[0]
     announce(f"goe512 full launch ({n + 1} problems)")
     lam, mu, W, flag = run_all([A])[0]
@@ -82,7 +82,7 @@ def test_goe512_all_minors():
 
 
 def test_uneven_batch_of_256():
-    mats = inputs.make_config(3)
+    mats = inputs.make_workload("uneven256")
     sizes = [m.shape[0] for m in mats]
     announce(f"uneven batch of {len(mats)} (sizes {min(sizes)}..{max(sizes)}, {sum(sizes)} minors)")
     res = run_all(mats)
@@ -199,7 +199,7 @@ def test_gue4096_sampled_minors(form):
     import torch
     from paper_2002_04989_amd import eeid
     g = golden("gue4096")
-    A = inputs.make_config(5)[0]
+    A = inputs.make_workload("gue4096")[0]
     js = [int(j) for j in g["js"]]
     announce(f"gue4096 {form}: lambda(A) + minors {js}")
     lam, mu, flag = eeid.minor_eigvals_subset(torch.from_numpy(A).cuda(), js, prec=form)
@@ -220,7 +220,7 @@ def test_gue4096_sampled_minors(form):
 
 @pytest.mark.parametrize("form", ["fp64", "fp32"])
 def test_gue4096_every_component(form):
-    """Config 5 in full: lambda(A), all 4096 minors and all 4096^2 components.
+    """Complex Hermitian n = 4096 in full: lambda(A), all 4096 minors and all 4096^2 components.
     The minors run in chunks of about 820 (one persistent launch each, so that
     progress is reported between launches), then Eq. (2) over all of them.
     Checked against the stored oracle values (lambda, the sampled minors and
@@ -231,7 +231,7 @@ def test_gue4096_every_component(form):
     import torch
     from paper_2002_04989_amd import eeid
     g = golden("gue4096")
-    A = inputs.make_config(5)[0]
+    A = inputs.make_workload("gue4096")[0]
     n = A.shape[0]
     dA = torch.from_numpy(A).to("cuda:0")
     announce(f"gue4096 {form}: lambda(A) and minor 0")
