@@ -177,11 +177,11 @@ def errors(mats, truth, lam, mu, V2, n):
 
 
 def run_form(mats_dev, n, form, steps, warmup, tune=True, graph=True):
-    """Warm-up (including the recording of the graphs), then `steps` timed
-    steps: the eigenvalue launch and the identity launch, each a hipGraph
-    replay in graph mode (the batch packed and the outputs allocated once, so
-    every step replays the same recording), with HIP events on the stream
-    around each."""
+    """Recording of the graphs (untimed, like the autotuning), `warmup`
+    untimed steps, then `steps` timed steps: the eigenvalue launch and the
+    identity launch, each a hipGraph replay in graph mode (the batch packed and
+    the outputs allocated once, so every step replays the same recording), with
+    HIP events on the stream around each."""
     import torch
     from paper_2002_04989_amd import eeid
     stream = torch.cuda.current_stream()
@@ -206,6 +206,13 @@ def run_form(mats_dev, n, form, steps, warmup, tune=True, graph=True):
 
     eeid.set_graph_mode(graph)
     try:
+        if graph:
+            # recording, before the warm-up: the identity's first call uploads its
+            # tables, which invalidates the eigenvalue launch recorded just before
+            # (recordings are keyed on the handle's buffers); the second call pair
+            # records both for good
+            step()
+            step()
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
