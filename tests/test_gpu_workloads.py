@@ -21,8 +21,8 @@ at any size:
   in chunks of launches), checked against the stored columns and the exact
   invariants on the whole W.
 * real n=4700 (both two-stage configurations): lambda(A) and two minors
-  against the oracle's LAPACK mode, and interlacing; at this order the
-  bisection's LDS region sets the kernel's LDS size.
+  against stored oracle values (double-precision Jacobi), and interlacing;
+  at this order the bisection's LDS region sets the kernel's LDS size.
 
 Tolerances, FP64 forms: eigenvalues 1e-10 ||A||_2, |v_ij|^2 1e-9 absolute,
 against the oracle and, for the clustered matrix, also against its exact
@@ -274,18 +274,18 @@ def test_gue4096_every_component(form):
 
 @pytest.fixture(scope="module")
 def large_real():
-    n = 4700
-    A = inputs.goe(n, 47)
-    js = [0, 2351]
-    # LAPACK mode of the oracle (the Jacobi mode would take tens of minutes here)
-    return A, js, oracle.eigvalsh(A, "lapack"), oracle.minor_spectra(A, js, "lapack")
+    # stored oracle values (double-precision Jacobi, tests/golden/make_golden.py)
+    g = golden("goe4700")
+    A = inputs.goe(4700, 47)
+    js = [int(j) for j in g["js"]]
+    return A, js, g["lam"], g["mu"]
 
 
 @pytest.mark.parametrize("variant", ["band32_nt512", "band32_nt256x2"])
 def test_large_real_order(large_real, variant):
     """n = 4700 (padded order 4736): the bisection's LDS region (two doubles per
     row) is then larger than the chase's and sets the LDS size; lambda(A) and
-    two minors against the oracle, and Cauchy interlacing."""
+    two minors against the stored oracle values, and Cauchy interlacing."""
     import torch
     from paper_2002_04989_amd import eeid
     A, js, lam_o, mu_o = large_real
