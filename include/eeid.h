@@ -145,16 +145,18 @@ eeid_status_t eeid_minor_eigvals_subset(eeid_handle_t h, eeid_dtype_t t, eeid_pr
 /* lambda(A) and the spectra of a few minors of ONE real symmetric matrix with
  * low latency (the single-component and single-column queries of Section 4,
  * Table 1, Fig. 1(a)): each eigenvalue problem is spread over many
- * workgroups (one per CU, the CUs split evenly over the problems) instead of
- * one, in one cooperative launch: unblocked Householder tridiagonalisation
+ * workgroups (one per CU, the CUs split evenly over the problems, at most
+ * one per 16 rows) instead of one, in one cooperative launch: unblocked
+ * Householder tridiagonalisation
  * with the matrix rows dealt cyclically to the workgroups (two grid-wide
  * barriers per column, each bounded: a wait that gives up sets
  * EEID_FLAG_WAIT_TIMEOUT), then each workgroup bisects its slice of the
  * eigenvalues.  Arguments as for eeid_minor_eigvals_subset (nsel may be 0);
  * at most 16 problems per call (lambda counts as one); EEID_R64 and
  * EEID_PREC_FP64 only, else EEID_ERR_UNSUPPORTED.  The same request gives the
- * same bits on every call (the workgroups per problem depend on the number of
- * problems, so other requests agree to rounding, as does the batched path). */
+ * same bits on every call (the workgroups per problem depend on the order and
+ * the number of problems, so other requests agree to rounding, as does the
+ * batched path). */
 eeid_status_t eeid_minor_eigvals_latency(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p,
                                          int64_t n, const void *A, int64_t nsel, const int64_t *js,
                                          double *lambda, double *mu_sel, int32_t *flag);

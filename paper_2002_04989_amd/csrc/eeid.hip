@@ -679,8 +679,11 @@ eeid_status_t eeid_minor_eigvals_latency(eeid_handle_t h, eeid_dtype_t t, eeid_p
     int per_cu = 0;
     HIP_TRY(h, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, eeid::LAT_NT, lds));
     if (per_cu < 1) return fail(h, EEID_ERR_UNSUPPORTED, "latency kernel cannot be resident");
-    // one workgroup per CU, split evenly over the problems
-    const int G = std::max(1, h->cu_count / std::max(P, 1));
+    // one workgroup per CU, split evenly over the problems, but at least 16
+    // rows per workgroup: below that a grid barrier's arrivals cost more than
+    // the rows' work (n = 502: 7.7 ms with 64 workgroups per problem, 10.3 ms
+    // with 128; from n = 2002 on, every CU pays)
+    const int G = std::max(1, std::min(h->cu_count / std::max(P, 1), (int)((n + 15) / 16)));
     const int64_t pb = eeid::lat_prob_bytes(LD, G);
     if (P > 0) {
         s = ensure(h, h->lat_work, (size_t)(pb * P));
