@@ -434,6 +434,39 @@ def test_graph_mode_separate_entry_points(prec):
         eeid.set_graph_mode(False)
 
 
+def test_graph_cache_replaces_old_recordings():
+    """More argument sets than the handle keeps recordings of (eight): each
+    batch is recorded, later replaced, recorded again when it returns, and
+    every replay matches the eager result bit for bit."""
+    import torch
+    from paper_2002_04989_amd import eeid
+    announce("graph cache: 12 argument sets, two passes")
+    batches = [[torch.from_numpy(inputs.goe(20 + 7 * b, 60 + b)).cuda()] for b in range(12)]
+    packed = [eeid.pack(m) for m in batches]
+    ref = []
+    for pk in packed:
+        lam, mu, fl = eeid.minor_eigvals(pk, "fp64")
+        torch.cuda.synchronize()
+        ref.append((lam.cpu().numpy(), mu.cpu().numpy()))
+    outs = []
+    for pk in packed:
+        nl, nm, _ = eeid.sizes(pk.n)
+        outs.append((torch.empty(nl, dtype=torch.float64, device="cuda"),
+                     torch.empty(max(nm, 1), dtype=torch.float64, device="cuda"),
+                     torch.empty(1, dtype=torch.int32, device="cuda")))
+    eeid.set_graph_mode(True)
+    try:
+        for rep in range(2):
+            for b, pk in enumerate(packed):
+                lam, mu, fl = eeid.minor_eigvals(pk, "fp64", out=outs[b])
+                torch.cuda.synchronize()
+                np.testing.assert_array_equal(lam.cpu().numpy(), ref[b][0], err_msg=f"pass {rep} batch {b}")
+                np.testing.assert_array_equal(mu.cpu().numpy(), ref[b][1], err_msg=f"pass {rep} batch {b}")
+                assert int(fl.cpu()[0]) == 0
+    finally:
+        eeid.set_graph_mode(False)
+
+
 def test_autotune_picks_a_variant_and_results_hold():
     from paper_2002_04989_amd import eeid
     mats = [inputs.goe(130, 8), inputs.goe(64, 9)]
