@@ -8,6 +8,8 @@
 //     form I - V T V^T), then the two-sided update of the trailing matrix
 //     A22 <- Q^T A22 Q = A22 - V W^T - W V^T with Y = A22 V (two MFMA passes
 //     over the stored lower triangle), X = Y T, W = X - 1/2 V (T^T V^T X);
+//     with an FP64 trailing matrix the panels go in pairs that share one
+//     update (see reduce_to_band);
 //   stage 2, band -> tridiagonal by Householder bulge chasing: sweep s removes
 //     column s below the subdiagonal; each step of a sweep applies the
 //     previous reflector from the right to the BW x BW block below it,
@@ -18,10 +20,11 @@
 //   one-stage kernel.
 //
 // The one-stage reduction streams the whole trailing triangle from HBM once
-// per column; here it is read three times per panel of BW columns (two SYMM
-// passes and the read-modify-write of the update), so HBM traffic drops by
-// about BW / 4.  Both stages are orthogonal similarities, so the eigenvalues
-// are those of the problem up to backward-stable rounding.
+// per column; here it is read twice per panel of BW columns for the SYMM and
+// read and written once per pair of panels (once per panel with an FP32
+// trailing matrix) for the update, so HBM traffic drops by about BW / 3.
+// Both stages are orthogonal similarities, so the eigenvalues are those of
+// the problem up to backward-stable rounding.
 //
 // Trailing-matrix storage (S = double or float): the lower triangle in 64x64
 // tiles as in eeid_tridiag.hpp, but inside a tile 8x4 micro-tiles (8 rows,
