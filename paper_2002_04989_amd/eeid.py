@@ -283,7 +283,10 @@ def components_subset(lam, mu_sel, flag):
 
 
 def set_graph_mode(enable: bool, device: int | None = None):
-    """Record eeid_all_components into a hipGraph per argument set and replay it."""
+    """Graph mode for minor_eigvals, components and all_components: each argument
+    set (pointers, orders, kernel configuration) is recorded into a hipGraph once
+    and replayed afterwards (pass a pack()ed batch and out= buffers so that
+    repeated calls present the same pointers)."""
     h = handle(device)
     _check(load_library().eeid_set_graph_mode(h, 1 if enable else 0), h)
 
