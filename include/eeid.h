@@ -205,6 +205,20 @@ eeid_status_t eeid_components_noalloc(eeid_handle_t h, int64_t count, const int6
 eeid_status_t eeid_components_subset(eeid_handle_t h, int64_t n, const double *lambda, int64_t nsel,
                                      const double *mu_sel, double *V2_sel, int32_t *flag);
 
+/* One component |v_ij|^2 of ONE real symmetric matrix: the paper's scalar
+ * query EigenComponent(matrix, i, j) (Section 3, Algorithms 1 and 2; Section
+ * 4, Table 1).  lambda(A) and the spectrum of the minor M_j on the latency
+ * path (as eeid_minor_eigvals_latency), then Eq. (2) for the pair (i, j) in
+ * the handle's identity form; bit for bit entry i of the column that
+ * eeid_components_subset gives for j.
+ *   A    device, n x n row-major, lower triangle read;  0 <= i, j < n
+ *   out  device double [1] output;  flag device int32 [1] output (flags as
+ *        for eeid_minor_eigvals)
+ * EEID_R64 and EEID_PREC_FP64 only, else EEID_ERR_UNSUPPORTED; the spectra
+ * live in workspace the handle owns. */
+eeid_status_t eeid_component(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64_t n, const void *A, int64_t i,
+                             int64_t j, double *out, int32_t *flag);
+
 /* One eigenvector's squared components (the complete-eigenvector query of
  * Section 4, Fig. 1(b)): row i of Eq. (2), row[j] = |v_ij|^2 for every j, from
  * lambda(A) and the spectra of all n minors (as eeid_minor_eigvals writes

@@ -66,6 +66,7 @@ struct eeid_handle_s {
     int cu_count = 0;
     std::string err;
     Buf work, items, desc, desc_sub, dpair, dpair_sub, lam_ready, sbuf, lat_work, lat_items, lat_bar;
+    Buf comp;   // eeid_component: lambda, mu and the column of its matrix
     int *counter = nullptr;
     char *scratch_ptr = nullptr;   // this device's copy of `scratch` (hipGetSymbolAddress at create)
     std::vector<int64_t> items_key, desc_key, desc_sub_key;
@@ -517,7 +518,7 @@ eeid_status_t eeid_destroy(eeid_handle_t h) {
     for (const auto &g : h->graphs) (void)hipGraphExecDestroy(g.exec);
     if (h->gstream) (void)hipStreamDestroy(h->gstream);
     Buf *bufs[] = {&h->work,     &h->items,     &h->desc,    &h->desc_sub, &h->dpair, &h->dpair_sub,
-                   &h->lam_ready, &h->sbuf, &h->lat_work, &h->lat_items, &h->lat_bar};
+                   &h->lam_ready, &h->sbuf, &h->lat_work, &h->lat_items, &h->lat_bar, &h->comp};
     for (Buf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (h->counter) (void)hipFree(h->counter);
@@ -814,6 +815,25 @@ eeid_status_t eeid_eigenvector_sq(eeid_handle_t h, int64_t n, const double *lamb
         hipLaunchKernelGGL(eeid::eigenvector_row_kernel<false>, grid, dim3(256), 0, h->stream, (int)n, (int)i, lambda,
                            mu, row, flag);
     HIP_TRY(h, hipGetLastError());
+    return EEID_OK;
+}
+
+eeid_status_t eeid_component(eeid_handle_t h, eeid_dtype_t t, eeid_prec_t p, int64_t n, const void *A, int64_t i,
+                             int64_t j, double *out, int32_t *flag) {
+    if (!h) return EEID_ERR_INVALID_ARG;
+    if (n < 1) return fail(h, EEID_ERR_INVALID_ARG, "n must be >= 1");
+    if (i < 0 || i >= n || j < 0 || j >= n) return fail(h, EEID_ERR_INVALID_ARG, "index i or j out of range");
+    if (!A || !out || !flag) return fail(h, EEID_ERR_INVALID_ARG, "null pointer argument");
+    HIP_TRY(h, hipSetDevice(h->device));
+    // lambda [n], mu [n - 1] (at least one slot), the column [n]
+    eeid_status_t s = ensure(h, h->comp, sizeof(double) * (size_t)(3 * n));
+    if (s != EEID_OK) return s;
+    double *lam = reinterpret_cast<double *>(h->comp.p), *mu = lam + n, *col = mu + n;
+    s = eeid_minor_eigvals_latency(h, t, p, n, A, 1, &j, lam, mu, flag);
+    if (s != EEID_OK) return s;
+    s = eeid_components_subset(h, n, lam, 1, mu, col, flag);
+    if (s != EEID_OK) return s;
+    HIP_TRY(h, hipMemcpyAsync(out, col + i, sizeof(double), hipMemcpyDeviceToDevice, h->stream));
     return EEID_OK;
 }
 

@@ -31,7 +31,7 @@ EXPORTS = (
     "eeid_set_graph_mode",
     "eeid_variant_count", "eeid_set_variant", "eeid_set_identity_form",
     "eeid_rotated_minor_eigvals", "eeid_signed_eigenvectors", "eeid_eigenvector_sq",
-    "eeid_minor_eigvals_latency", "eeid_phase_ticks",
+    "eeid_minor_eigvals_latency", "eeid_component", "eeid_phase_ticks",
     "eeid_autotune",
 )
 VARIANTS = ("nb32_nt512", "nb32_nt256x2", "nb16_nt512", "band32_nt512", "band32_nt256x2")
@@ -78,6 +78,7 @@ def load_library(path: str = LIB_PATH):
     lib.eeid_set_identity_form.argtypes = [_vp, c]
     lib.eeid_minor_eigvals_latency.argtypes = [_vp, c, c, ctypes.c_int64, _vp, ctypes.c_int64, _i64p,
                                                _vp, _vp, _vp]
+    lib.eeid_component.argtypes = [_vp, c, c, ctypes.c_int64, _vp, ctypes.c_int64, ctypes.c_int64, _vp, _vp]
     lib.eeid_phase_ticks.argtypes = [ctypes.POINTER(ctypes.c_ulonglong), c]
     lib.eeid_eigenvector_sq.argtypes = [_vp, ctypes.c_int64, _vp, _vp, ctypes.c_int64, _vp, _vp]
     lib.eeid_rotated_minor_eigvals.argtypes = [_vp, c, c, ctypes.c_int64, _vp, ctypes.c_int64, _vp, _vp]
@@ -235,6 +236,22 @@ def minor_eigvals_latency(A, js: Sequence[int], prec: str = "fp64", with_lambda:
         h, _dtype_code(A), PREC[prec], n, A.data_ptr(), len(js), _i64(js) if len(js) else None,
         lam.data_ptr() if lam is not None else None, mu.data_ptr(), flag.data_ptr()), h)
     return lam, mu[:len(js), :n - 1], flag
+
+
+def component(A, i: int, j: int, prec: str = "fp64"):
+    """|v_ij|^2 of one real symmetric matrix (the paper's EigenComponent(matrix, i, j)):
+    (a one-element device tensor, flag)."""
+    import torch
+    if not A.is_cuda or A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("A must be a square GPU tensor")
+    A = A.contiguous()
+    n = int(A.shape[0])
+    out = torch.empty(1, dtype=torch.float64, device=A.device)
+    flag = torch.empty(1, dtype=torch.int32, device=A.device)
+    h = handle(A.device.index)
+    _check(load_library().eeid_component(h, _dtype_code(A), PREC[prec], n, A.data_ptr(), int(i), int(j),
+                                         out.data_ptr(), flag.data_ptr()), h)
+    return out, flag
 
 
 def component_column(A, j: int):

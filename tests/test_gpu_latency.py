@@ -92,6 +92,40 @@ def test_single_component_against_the_oracle():
     np.testing.assert_allclose(col.cpu().numpy(), W_def[:, j], atol=1e-9, rtol=0)
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 130, 300])
+def test_scalar_component_query(n):
+    """eeid_component(i, j): bit for bit entry i of the column query's column j,
+    and the plain definition |V_ji|^2 of the oracle's eigenvectors."""
+    import torch
+    from paper_2002_04989_amd import eeid
+    A = inputs.goe(n, 900 + n)
+    announce(f"scalar component query n={n}")
+    dA = torch.from_numpy(A).to("cuda:0")
+    _, W_def = oracle.components_definition(A)
+    pairs = sorted({(0, 0), (n - 1, 0), (0, n - 1), (n // 2, n // 3), (n - 1, n - 1)})
+    for i, j in pairs:
+        w, f = eeid.component(dA, i, j)
+        col, _, _, fc = eeid.component_column(dA, j)
+        torch.cuda.synchronize()
+        assert int(f.cpu()[0]) == 0 and int(fc.cpu()[0]) == 0
+        np.testing.assert_array_equal(w.cpu().numpy()[0], col.cpu().numpy()[i], err_msg=f"(i, j) = ({i}, {j})")
+        assert abs(float(w.cpu()[0]) - W_def[i, j]) < 1e-9, (i, j)
+
+
+def test_scalar_component_refusals():
+    import torch
+    from paper_2002_04989_amd import eeid
+    announce("scalar component query: refusals")
+    A = torch.from_numpy(inputs.goe(8, 3)).to("cuda:0")
+    for i, j in ((-1, 0), (0, 8), (8, 0)):
+        with pytest.raises(eeid.EEIDError) as e:
+            eeid.component(A, i, j)
+        assert e.value.status == 1   # EEID_ERR_INVALID_ARG
+    with pytest.raises(eeid.EEIDError) as e:
+        eeid.component(torch.from_numpy(inputs.gue(8, 3)).to("cuda:0"), 0, 0)
+    assert e.value.status == 5       # EEID_ERR_UNSUPPORTED
+
+
 def test_reruns_are_bitwise_identical_and_lambda_optional():
     n = 513
     A = inputs.goe(n, 8)
