@@ -337,6 +337,23 @@ def cpu_baseline(mats, rounds=128, max_threads=16):
     }
 
 
+def oracle_single_component(n=502):
+    """The oracle on the single-component query (part of the CPU baseline):
+    lambda(A) and M_j of the GOE (seed 11) of order n by the extended-precision
+    Jacobi, both problems on two threads at once, then the log-sum column of
+    Eq. (2).  Returns (n, seconds)."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_2002_04989_amd import inputs
+    A = inputs.goe(n, 11)
+    j = n // 2
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(2) as ex:
+        lam, mu = ex.map(lambda M: oracle.eigvalsh(M), [A, oracle.minor(A, j)])
+    oracle.identity_from_spectra(lam, mu[None, :])
+    return n, time.perf_counter() - t0
+
+
 def host_library(mats, budget_s=8.0):
     """Context, not the oracle: numpy/LAPACK eigvalsh for the EigenValues step on this host."""
     import numpy as np
@@ -486,18 +503,15 @@ PAPER_TABLE1 = {502: (0.170962, 0.119722), 1002: (1.100800, 0.595935), 2002: (9.
                 6002: (229.338600, 50.682400)}
 
 
-def single_component_latency(sizes=(502, 1002, 2002, 3002, 4002, 5002, 6002), reps=3, oracle_n=502):
+def single_component_latency(sizes=(502, 1002, 2002, 3002, 4002, 5002, 6002), reps=3, oracle_time=None):
     """The single-component query of Table 1 (lambda(A) + the spectrum of one minor
     M_j + Eq. (2), here for every i of column j at once) on one GOE matrix per
     size: the latency path (each problem over many workgroups) against the
     batched path (one workgroup per problem), wall time from device-resident A
-    to device-resident column; and the oracle (extended-precision Jacobi, both
-    problems on two threads at once, plus the log-sum column) at oracle_n,
-    scaled by n^3 to the other sizes."""
+    to device-resident column.  oracle_time: (n, seconds) of the oracle on the
+    same query (timed in the CPU-baseline leg), scaled by n^3 to every size."""
     import numpy as np
     import torch
-    import oracle
-    from concurrent.futures import ThreadPoolExecutor
     from paper_2002_04989_amd import eeid, inputs
     rows = []
     for n in sizes:
@@ -527,16 +541,9 @@ def single_component_latency(sizes=(502, 1002, 2002, 3002, 4002, 5002, 6002), re
         del A
     out = {"workload": "GOE (seed 11) of each order n, one minor j = n // 2; lambda(A) + mu(M_j) + column j of W",
            "rows": rows, "paper_hardware": "Intel Xeon E3-1270 v6, 4 cores / 8 threads (context only)"}
-    if oracle_n is None:
+    if oracle_time is None:
         return out
-    # the oracle at oracle_n: lambda(A) and M_j by Jacobi on two threads, then the column
-    A = inputs.goe(oracle_n, 11)
-    j = oracle_n // 2
-    t0 = time.perf_counter()
-    with ThreadPoolExecutor(2) as ex:
-        lam, mu = ex.map(lambda M: oracle.eigvalsh(M), [A, oracle.minor(A, j)])
-    oracle.identity_from_spectra(lam, mu[None, :])
-    t_or = time.perf_counter() - t0
+    oracle_n, t_or = oracle_time
     for row in rows:
         row["oracle_s"] = round(t_or * (row["n"] / oracle_n) ** 3, 2)
         row["oracle_kind"] = "measured" if row["n"] == oracle_n else f"n^3-scaled from the measured n={oracle_n}"
@@ -644,16 +651,18 @@ def main():
         others = other_workloads()
         log("complex n=4096 (one wave of its problems)")
         others["complex4096"] = complex4096()
-    latency = None
-    if not args.no_latency:
-        log("single-component latency (Table 1 sizes)")
-        latency = single_component_latency(oracle_n=None if args.no_cpu else 502)
-    cpu = hostlib = None
+    cpu = hostlib = oracle_sc = None
     if not args.no_cpu:
         log("cpu baseline (oracle) on a bounded sample")
         cpu = cpu_baseline(mats)
+        oracle_sc = oracle_single_component()
+        cpu["single_component_n502_s"] = round(oracle_sc[1], 2)
         log("host library context (LAPACK)")
         hostlib = host_library(mats)
+    latency = None
+    if not args.no_latency:
+        log("single-component latency (Table 1 sizes)")
+        latency = single_component_latency(oracle_time=oracle_sc)
 
     out = {
         "metric": METRIC, "value": value, "unit": "components/s", "n_gpus": 1, "steps": args.steps,
